@@ -1,0 +1,186 @@
+/*
+ * nsfr.h -- C ABI of libnsfr, the MI355X (gfx950) implementation of the
+ * right-hand side of the nonlinearly stable flux reconstruction (NSFR) scheme
+ * for 3D compressible Euler on curvilinear hexahedra (Cicchino & Nadarajah,
+ * arXiv 2312.07725).
+ *
+ * Discretisation (all FP64):
+ *   - solution, volume and surface quadrature on the p+1 Legendre-Gauss-Lobatto
+ *     (LGL) nodes per direction, nodal Lagrange basis (Sec. 2.2, Sec. 6);
+ *   - volume term: entropy-conserving two-point flux differencing, the
+ *     Hadamard product of the hybridised skew-symmetric operator with the
+ *     metric-split reference two-point flux (Eq. NSFR), evaluated line by
+ *     line (Sec. 5, sum-factorised Hadamard product);
+ *   - surface term: the same two-point flux (optionally plus local
+ *     Lax-Friedrichs dissipation) at shared face nodes, lifted by the
+ *     FR-modified mass (Eq. NSFR, last term; Sec. 3.2);
+ *   - mass: weight-adjusted inverse Pi~ (W J)^-1 Pi~^T of the FR-modified mass
+ *     (Eq. weight-adj ESFR mass, Eq. Fr projection);
+ *   - time: classical four-stage RK4 (Sec. 6).
+ *
+ * Data layout. Every state-sized array is contiguous FP64 device memory of
+ * 5 * E * (p+1)^3 doubles in the order [state][element][k][j][i], i (xi)
+ * fastest; state = (rho, rho u, rho v, rho w, rho e); element
+ * e = ex + nx * (ey + ny * ez). Arrays must be 8-byte aligned.
+ *
+ * Ownership. The caller allocates and owns every array passed in. The library
+ * owns what it allocates in nsfr_create (operators, metrics, a residual-sized
+ * workspace) and frees it in nsfr_destroy. nsfr_rhs, nsfr_residual,
+ * nsfr_rk4_step, nsfr_rk4_run and nsfr_rhs_vjp allocate nothing.
+ *
+ * Streams. All work is enqueued asynchronously on the context's HIP stream
+ * (nsfr_create / nsfr_set_stream); only nsfr_check_state and the ensemble
+ * constructors synchronise. A context is used by one host thread at a time.
+ *
+ * Errors. Every call returns an nsfr_status; no exception crosses the ABI.
+ * Arguments are validated before any launch. nsfr_last_error() returns a
+ * thread-local description of the most recent failure.
+ */
+#ifndef NSFR_H
+#define NSFR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    NSFR_OK = 0,
+    NSFR_EINVAL = -1,        /* bad argument or configuration                 */
+    NSFR_ENOMEM = -2,        /* device allocation failed                      */
+    NSFR_EHIP = -3,          /* a HIP runtime call or kernel launch failed    */
+    NSFR_EUNPHYSICAL = -4,   /* non-positive density or pressure, or NaN      */
+    NSFR_ENOTSUP = -5        /* valid request this build does not implement   */
+} nsfr_status;
+
+typedef struct {
+    int32_t p;            /* polynomial degree, 2..5 (n = p+1 LGL nodes per direction)   */
+    int32_t ne[3];        /* elements per direction of the periodic box, each >= 1       */
+    double lo, hi;        /* box [lo, hi]^3 (TGV: [0, 2 pi]; MMS: [-1, 1])               */
+    double warp_beta;     /* amplitude of the nonsymmetric warp, Eq. warped grid         */
+    double warp_l;        /* warp length l; <= 0 selects (hi - lo) / (2 pi)              */
+    double gamma;         /* ratio of specific heats (1.4)                               */
+    double c_fr;          /* FR parameter c in the convention of Eq. Km (1D K = 2c d d^T) */
+    int32_t flux;         /* 0: Chandrashekar flux with Ranocha's pressure fix (arithmetic
+                             mean pressure); 1: plain Chandrashekar flux                 */
+    int32_t surface_diss; /* 0: entropy-conserving surface flux; 1: plus local
+                             Lax-Friedrichs dissipation                                  */
+    int32_t source;       /* 0: none; 1: manufactured-solution source of Sec. 6.1        */
+    int32_t tile;         /* elements per workgroup of the stage kernel; 0 = default     */
+} nsfr_config;
+
+typedef struct nsfr_ctx nsfr_ctx;
+
+/* Create a context on the current HIP device: builds the 1D LGL operators on
+ * the host, the warped mesh, conservative-curl metric terms (Sec. 2.2, Eq. GCL)
+ * and 1/(W J) on the device, and allocates the workspace. hip_stream may be
+ * NULL (default stream). Errors: NSFR_EINVAL (p outside 2..5, ne < 1, hi <= lo,
+ * gamma <= 1, flux/surface_diss/source out of range, negative tile),
+ * NSFR_ENOMEM, NSFR_EHIP, NSFR_EUNPHYSICAL if some node has J <= 0. */
+nsfr_status nsfr_create(const nsfr_config* cfg, void* hip_stream, nsfr_ctx** out);
+nsfr_status nsfr_destroy(nsfr_ctx* ctx);
+nsfr_status nsfr_set_stream(nsfr_ctx* ctx, void* hip_stream);
+
+/* Number of elements and nodes per element ((p+1)^3). Host pointers. */
+nsfr_status nsfr_sizes(const nsfr_ctx* ctx, int64_t* n_elem, int64_t* n_node_per_elem);
+
+/* Physical node coordinates, device array [3][E][(p+1)^3] (Eq. warped grid at
+ * the LGL nodes). */
+nsfr_status nsfr_node_coords(nsfr_ctx* ctx, double* xyz);
+
+/* Metric cofactor matrix and Jacobian at the nodes (Sec. 2.2): C is a device
+ * array [3][3][E][(p+1)^3] with C[n][i] = (J a^i)_n, J is [E][(p+1)^3]. */
+nsfr_status nsfr_geometry(nsfr_ctx* ctx, double* C, double* J);
+
+/* Pre-mass residual R = R_vol + R_surf - W J q(t) of Eq. NSFR, so that
+ * (M_m + K_m) dU/dt = -R. U and R are state-sized device arrays (R may not
+ * alias U). t is used only by the manufactured source. */
+nsfr_status nsfr_residual(nsfr_ctx* ctx, const double* U, double* R, double t);
+
+/* dU/dt = -Pi~ (W J)^-1 Pi~^T R(U, t) (Eq. weight-adj ESFR mass). dUdt may not
+ * alias U. */
+nsfr_status nsfr_rhs(nsfr_ctx* ctx, const double* U, double* dUdt, double t);
+
+/* One classical RK4 step, in place on U, with the step size read from device
+ * memory dt_dev (one double) so that the launch sequence is static. work is a
+ * caller-owned device array of 3 state-sized arrays (15 * E * (p+1)^3
+ * doubles). t is the time at the start of the step (source only). */
+nsfr_status nsfr_rk4_step(nsfr_ctx* ctx, double* U, const double* dt_dev, double t, double* work);
+
+/* nsteps RK4 steps replayed from a HIP graph of one step (the four stage
+ * kernels). The time is read from and advanced in device memory t_dev (one
+ * double) by dt each step; t_dev may be NULL when the configuration has no
+ * source term (then the graph holds the stage kernels only). The graph is
+ * built on first use for a given (U, dt_dev, t_dev, work) and kept in the
+ * context. */
+nsfr_status nsfr_rk4_run(nsfr_ctx* ctx, double* U, const double* dt_dev, double* t_dev,
+                         int32_t nsteps, double* work);
+
+/* lam_dev[0] = max over nodes of |u| + sqrt(gamma p / rho). */
+nsfr_status nsfr_max_wavespeed(nsfr_ctx* ctx, const double* U, double* lam_dev);
+
+/* dt_dev[0] = cfl * (hi - lo) / (ne[0] (p+1)) / (max wave speed) (Sec. 6). */
+nsfr_status nsfr_cfl_dt(nsfr_ctx* ctx, const double* U, double cfl, double* dt_dev);
+
+/* Vector-Jacobian product g = (d(dU/dt)/dU)^T lam of nsfr_rhs at (U, t),
+ * including the Jacobians of the two-point volume and surface fluxes. The
+ * weight-adjusted inverse is symmetric, so g = -(dR/dU)^T (A lam). g may not
+ * alias U or lam. */
+nsfr_status nsfr_rhs_vjp(nsfr_ctx* ctx, const double* U, const double* lam, double* g, double t);
+
+/* Discrete adjoint of one RK4 step: given U^n, the step size and
+ * lam_next = dJ/dU^{n+1}, writes lam = dJ/dU^n (may alias lam_next). work is
+ * a caller-owned device array of 6 state-sized arrays. */
+nsfr_status nsfr_rk4_step_vjp(nsfr_ctx* ctx, const double* U, const double* dt_dev, double t,
+                              const double* lam_next, double* lam, double* work);
+
+/* Diagnostics of R(U, t) (Sec. 5.2, 5.3, 6.3) into device array out (8 doubles):
+ * [sum v.R, sum |v.R|, sum R_rho, sum R_mx, sum R_my, sum R_mz, sum R_E, max |R|],
+ * v the entropy variables. Uses the library workspace. */
+nsfr_status nsfr_diagnostics(nsfr_ctx* ctx, const double* U, double t, double* out);
+
+/* Kinetic energy J_KE = sum over nodes of W J rho |u|^2 / 2 into ke_dev[0]
+ * (device), and, if grad is not NULL, its gradient dJ_KE/dU (state-sized
+ * device array): W J [-|u|^2/2, u, v, w, 0]. The objective of the
+ * time-integrated sensitivity. */
+nsfr_status nsfr_kinetic_energy(nsfr_ctx* ctx, const double* U, double* ke_dev, double* grad);
+
+/* Synchronising state check: *bad_host = number of nodes with rho <= 0,
+ * p <= 0 or a NaN; returns NSFR_EUNPHYSICAL if that number is positive. */
+nsfr_status nsfr_check_state(nsfr_ctx* ctx, const double* U, int32_t* bad_host);
+
+/* ---- ensembles of independent flows, one launch per RK stage ------------ */
+typedef struct nsfr_ens nsfr_ens;
+
+/* n_flows configurations (any mix of p and ne). The packed state is the
+ * concatenation of the flows' state arrays; offsets (in doubles) are
+ * returned by nsfr_ens_offsets (n_flows + 1 entries, host). */
+nsfr_status nsfr_ens_create(const nsfr_config* cfgs, int32_t n_flows, void* hip_stream, nsfr_ens** out);
+nsfr_status nsfr_ens_destroy(nsfr_ens* ens);
+nsfr_status nsfr_ens_offsets(const nsfr_ens* ens, int64_t* offsets_host);
+/* Residual / rhs of every flow at time t in one launch. */
+nsfr_status nsfr_ens_rhs(nsfr_ens* ens, const double* U, double* dUdt, double t);
+/* One RK4 step of every flow, in place; dt_dev holds one step size per flow;
+ * work holds 3 packed-state-sized arrays. Four launches, one per stage. */
+nsfr_status nsfr_ens_rk4_step(nsfr_ens* ens, double* U, const double* dt_dev, double t, double* work);
+/* nsteps steps replayed from a HIP graph of one ensemble step. */
+nsfr_status nsfr_ens_rk4_run(nsfr_ens* ens, double* U, const double* dt_dev, double t,
+                             int32_t nsteps, double* work);
+/* Elements per work item for degree p (2..5) used by the ensemble kernel;
+ * epb = 0 restores the default. */
+nsfr_status nsfr_ens_set_tile(nsfr_ens* ens, int32_t p, int32_t epb);
+
+/* FR parameter c_HU (convention of Eq. Km) for degree p (2..5): the value for
+ * which the FR-modified 1D mass of the exactly integrated Lagrange basis on
+ * LGL nodes equals the collocated LGL mass (Sec. 6.2). c_HU = E_p / (2 (p!)^2)
+ * with E_p the LGL quadrature error of x^(2p). Host output. */
+nsfr_status nsfr_c_hu(int32_t p, double* c_out);
+
+const char* nsfr_status_string(nsfr_status s);
+const char* nsfr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NSFR_H */

@@ -1,0 +1,472 @@
+// C ABI of libnsfr: argument validation, context lifetime, launch sequences.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "nsfr_host.h"
+
+using namespace nsfr;
+
+namespace nsfr {
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+}  // namespace nsfr
+
+struct nsfr_ctx {
+    nsfr_config cfg;
+    int dev = 0;
+    hipStream_t stream = nullptr;
+    int p = 0, n = 0, n3 = 0;
+    int64_t E = 0;
+    HostOps hops;
+    Ops ops;
+    double* X = nullptr;       // [3][E][n3]
+    double* Cline = nullptr;   // [3][3][E][n3] line-major per direction
+    double* invWJ = nullptr;   // [E][n3]
+    double* J = nullptr;       // [E][n3]
+    double* wsR = nullptr;     // state-sized workspace
+    double* wsR2 = nullptr;    // state-sized workspace (adjoint)
+    double* red = nullptr;     // reduction partials
+    int nred = 0;
+    int32_t* cnt = nullptr;    // check_state counters (64)
+    int epb = 0;
+    // graph cache for nsfr_rk4_run
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    const void* gkey[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+
+#define HIP_TRY(call)                                                                         \
+    do {                                                                                      \
+        hipError_t _e = (call);                                                               \
+        if (_e != hipSuccess) {                                                               \
+            set_error(std::string(#call) + ": " + hipGetErrorString(_e));                     \
+            return NSFR_EHIP;                                                                 \
+        }                                                                                     \
+    } while (0)
+
+static nsfr_status bad(const char* msg) {
+    set_error(msg);
+    return NSFR_EINVAL;
+}
+
+static nsfr_status validate(const nsfr_config* c) {
+    if (!c) return bad("null config");
+    if (c->p < 2 || c->p > 5) return bad("p must be in 2..5");
+    for (int i = 0; i < 3; ++i)
+        if (c->ne[i] < 1) return bad("ne must be >= 1 in every direction");
+    if ((int64_t)c->ne[0] * c->ne[1] * c->ne[2] > (int64_t)1 << 31) return bad("too many elements");
+    if (!(c->hi > c->lo)) return bad("hi must exceed lo");
+    if (!(c->gamma > 1.0)) return bad("gamma must exceed 1");
+    if (!(c->c_fr >= 0.0) || !std::isfinite(c->c_fr)) return bad("c_fr must be finite and >= 0");
+    if (!std::isfinite(c->warp_beta)) return bad("warp_beta must be finite");
+    if (c->flux < 0 || c->flux > 1) return bad("flux must be 0 or 1");
+    if (c->surface_diss < 0 || c->surface_diss > 1) return bad("surface_diss must be 0 or 1");
+    if (c->source < 0 || c->source > 1) return bad("source must be 0 or 1");
+    if (c->tile < 0 || c->tile > max_epb(c->p)) return bad("tile out of range for this p");
+    return NSFR_OK;
+}
+
+static nsfr_status use_device(const nsfr_ctx* c) {
+    int cur = -1;
+    HIP_TRY(hipGetDevice(&cur));
+    if (cur != c->dev) HIP_TRY(hipSetDevice(c->dev));
+    return NSFR_OK;
+}
+
+static bool aligned(const void* p) { return p && ((uintptr_t)p % 8 == 0); }
+
+static void free_ctx(nsfr_ctx* c) {
+    if (!c) return;
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    double* bufs[] = {c->X, c->Cline, c->invWJ, c->J, c->wsR, c->wsR2, c->red};
+    for (double* b : bufs)
+        if (b) (void)hipFree(b);
+    if (c->cnt) (void)hipFree(c->cnt);
+    delete c;
+}
+
+static StageArgs base_args(const nsfr_ctx* c) {
+    StageArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.geo.nx = c->cfg.ne[0];
+    a.geo.ny = c->cfg.ne[1];
+    a.geo.nz = c->cfg.ne[2];
+    a.geo.E = c->E;
+    a.geo.Cline = c->Cline;
+    a.geo.invWJ = c->invWJ;
+    a.geo.X = c->X;
+    a.ops = c->ops;
+    a.gamma = c->cfg.gamma;
+    a.c1 = 1.0 / (2.0 * (c->cfg.gamma - 1.0));
+    a.epb = c->epb;
+    a.diss = c->cfg.surface_diss;
+    a.source = c->cfg.source;
+    return a;
+}
+
+static nsfr_status stage(nsfr_ctx* c, StageArgs& a) {
+    hipError_t e = launch_stage(c->p, c->cfg.c_fr != 0.0, c->cfg.flux, a, c->stream);
+    if (e != hipSuccess) {
+        set_error(std::string("stage kernel launch: ") + hipGetErrorString(e));
+        return NSFR_EHIP;
+    }
+    return NSFR_OK;
+}
+
+extern "C" {
+
+const char* nsfr_status_string(nsfr_status s) {
+    switch (s) {
+        case NSFR_OK: return "ok";
+        case NSFR_EINVAL: return "invalid argument";
+        case NSFR_ENOMEM: return "out of device memory";
+        case NSFR_EHIP: return "HIP runtime error";
+        case NSFR_EUNPHYSICAL: return "unphysical state";
+        case NSFR_ENOTSUP: return "not supported";
+    }
+    return "unknown status";
+}
+
+const char* nsfr_last_error(void) { return g_last_error.c_str(); }
+
+nsfr_status nsfr_create(const nsfr_config* cfg, void* hip_stream, nsfr_ctx** out) {
+    if (!out) return bad("null output pointer");
+    *out = nullptr;
+    nsfr_status st = validate(cfg);
+    if (st != NSFR_OK) return st;
+    nsfr_ctx* c = new nsfr_ctx();
+    c->cfg = *cfg;
+    c->stream = (hipStream_t)hip_stream;
+    c->p = cfg->p;
+    c->n = cfg->p + 1;
+    c->n3 = c->n * c->n * c->n;
+    c->E = (int64_t)cfg->ne[0] * cfg->ne[1] * cfg->ne[2];
+    c->epb = cfg->tile ? cfg->tile : default_epb(cfg->p);
+    build_ops(c->p, cfg->c_fr, c->ops, c->hops);
+    hipError_t he = hipGetDevice(&c->dev);
+    if (he != hipSuccess) {
+        set_error(std::string("hipGetDevice: ") + hipGetErrorString(he));
+        free_ctx(c);
+        return NSFR_EHIP;
+    }
+    const size_t nodes = (size_t)c->E * c->n3;
+    c->nred = 8 * 1024;
+    struct A { double** p; size_t n; } allocs[] = {
+        {&c->X, 3 * nodes}, {&c->Cline, 9 * nodes}, {&c->invWJ, nodes}, {&c->J, nodes},
+        {&c->wsR, 5 * nodes}, {&c->wsR2, 5 * nodes}, {&c->red, (size_t)c->nred}};
+    for (auto& al : allocs) {
+        if (hipMalloc((void**)al.p, al.n * sizeof(double)) != hipSuccess) {
+            set_error("hipMalloc failed for the context's device arrays");
+            free_ctx(c);
+            return NSFR_ENOMEM;
+        }
+    }
+    if (hipMalloc((void**)&c->cnt, 64 * sizeof(int32_t)) != hipSuccess) {
+        set_error("hipMalloc failed for the state-check counters");
+        free_ctx(c);
+        return NSFR_ENOMEM;
+    }
+    double l = cfg->warp_l > 0 ? cfg->warp_l : (cfg->hi - cfg->lo) / (2.0 * M_PI);
+    he = launch_geometry(c->p, c->ops, cfg->ne[0], cfg->ne[1], cfg->ne[2], cfg->lo, cfg->hi, cfg->warp_beta, l, c->X,
+                         c->Cline, c->invWJ, c->J, c->stream);
+    if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
+    if (he != hipSuccess) {
+        set_error(std::string("geometry setup: ") + hipGetErrorString(he));
+        free_ctx(c);
+        return NSFR_EHIP;
+    }
+    // every node must have a positive Jacobian
+    std::vector<double> J(nodes);
+    he = hipMemcpy(J.data(), c->J, nodes * sizeof(double), hipMemcpyDeviceToHost);
+    if (he != hipSuccess) {
+        set_error(std::string("geometry copy: ") + hipGetErrorString(he));
+        free_ctx(c);
+        return NSFR_EHIP;
+    }
+    for (double v : J)
+        if (!(v > 0.0)) {
+            set_error("the warped mesh has a node with J <= 0");
+            free_ctx(c);
+            return NSFR_EUNPHYSICAL;
+        }
+    *out = c;
+    return NSFR_OK;
+}
+
+nsfr_status nsfr_destroy(nsfr_ctx* c) {
+    if (!c) return bad("null context");
+    (void)use_device(c);
+    free_ctx(c);
+    return NSFR_OK;
+}
+
+nsfr_status nsfr_set_stream(nsfr_ctx* c, void* s) {
+    if (!c) return bad("null context");
+    c->stream = (hipStream_t)s;
+    return NSFR_OK;
+}
+
+nsfr_status nsfr_sizes(const nsfr_ctx* c, int64_t* ne, int64_t* nn) {
+    if (!c || !ne || !nn) return bad("null argument");
+    *ne = c->E;
+    *nn = c->n3;
+    return NSFR_OK;
+}
+
+nsfr_status nsfr_node_coords(nsfr_ctx* c, double* xyz) {
+    if (!c || !aligned(xyz)) return bad("null or misaligned argument");
+    nsfr_status st = use_device(c);
+    if (st) return st;
+    HIP_TRY(hipMemcpyAsync(xyz, c->X, 3 * (size_t)c->E * c->n3 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    return NSFR_OK;
+}
+
+nsfr_status nsfr_geometry(nsfr_ctx* c, double* C, double* J) {
+    if (!c || !aligned(C) || !aligned(J)) return bad("null or misaligned argument");
+    nsfr_status st = use_device(c);
+    if (st) return st;
+    HIP_TRY(launch_geometry_export(c->p, c->E, c->Cline, C, c->stream));
+    HIP_TRY(hipMemcpyAsync(J, c->J, (size_t)c->E * c->n3 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    return NSFR_OK;
+}
+
+nsfr_status nsfr_residual(nsfr_ctx* c, const double* U, double* R, double t) {
+    if (!c || !aligned(U) || !aligned(R) || U == R) return bad("null, misaligned or aliased argument");
+    nsfr_status st = use_device(c);
+    if (st) return st;
+    StageArgs a = base_args(c);
+    a.Uin = U;
+    a.out = R;
+    a.t = t;
+    a.mode = MODE_RESIDUAL;
+    return stage(c, a);
+}
+
+nsfr_status nsfr_rhs(nsfr_ctx* c, const double* U, double* dUdt, double t) {
+    if (!c || !aligned(U) || !aligned(dUdt) || U == dUdt) return bad("null, misaligned or aliased argument");
+    nsfr_status st = use_device(c);
+    if (st) return st;
+    StageArgs a = base_args(c);
+    a.Uin = U;
+    a.out = dUdt;
+    a.t = t;
+    a.mode = MODE_RHS;
+    return stage(c, a);
+}
+
+static nsfr_status rk4_enqueue(nsfr_ctx* c, double* U, const double* dt, double t, const double* tdev, double* work) {
+    const size_t ns = 5 * (size_t)c->E * c->n3;
+    double* acc = work;
+    double* Ya = work + ns;
+    double* Yb = work + 2 * ns;
+    StageArgs a = base_args(c);
+    a.dt = dt;
+    a.t = t;
+    a.tdev = tdev;
+    a.Un = U;
+    a.acc = acc;
+    nsfr_status st;
+    a.mode = MODE_RK1; a.Uin = U;  a.out = Ya; if ((st = stage(c, a))) return st;
+    a.mode = MODE_RK2; a.Uin = Ya; a.out = Yb; if ((st = stage(c, a))) return st;
+    a.mode = MODE_RK3; a.Uin = Yb; a.out = Ya; if ((st = stage(c, a))) return st;
+    a.mode = MODE_RK4; a.Uin = Ya; a.out = U;  return stage(c, a);
+}
+
+nsfr_status nsfr_rk4_step(nsfr_ctx* c, double* U, const double* dt, double t, double* work) {
+    if (!c || !aligned(U) || !aligned(dt) || !aligned(work)) return bad("null or misaligned argument");
+    nsfr_status st = use_device(c);
+    if (st) return st;
+    return rk4_enqueue(c, U, dt, t, nullptr, work);
+}
+
+nsfr_status nsfr_rk4_run(nsfr_ctx* c, double* U, const double* dt, double* tdev, int32_t nsteps, double* work) {
+    if (!c || !aligned(U) || !aligned(dt) || (tdev && !aligned(tdev)) || !aligned(work) || nsteps < 0)
+        return bad("null, misaligned or negative argument");
+    if (!tdev && c->cfg.source) return bad("t_dev is required when the source term is enabled");
+    nsfr_status st = use_device(c);
+    if (st) return st;
+    if (nsteps == 0) return NSFR_OK;
+    const void* key[4] = {U, dt, tdev, work};
+    if (!c->gexec || std::memcmp(key, c->gkey, sizeof(key)) != 0) {
+        if (c->gexec) { (void)hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }
+        if (c->graph) { (void)hipGraphDestroy(c->graph); c->graph = nullptr; }
+        hipStream_t cap;
+        HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        hipStream_t saved = c->stream;
+        c->stream = cap;
+        hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        nsfr_status s2 = NSFR_OK;
+        if (e == hipSuccess) {
+            s2 = rk4_enqueue(c, U, dt, 0.0, tdev, work);
+            if (s2 == NSFR_OK && tdev) {
+                hipError_t e2 = launch_advance_time(tdev, dt, cap);
+                if (e2 != hipSuccess) s2 = NSFR_EHIP;
+            }
+            hipError_t e3 = hipStreamEndCapture(cap, &c->graph);
+            if (e3 != hipSuccess && s2 == NSFR_OK) e = e3;
+        }
+        c->stream = saved;
+        (void)hipStreamDestroy(cap);
+        if (e != hipSuccess || s2 != NSFR_OK) {
+            set_error(std::string("graph capture failed: ") + hipGetErrorString(e));
+            return NSFR_EHIP;
+        }
+        HIP_TRY(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+        std::memcpy(c->gkey, key, sizeof(key));
+    }
+    for (int i = 0; i < nsteps; ++i) HIP_TRY(hipGraphLaunch(c->gexec, c->stream));
+    return NSFR_OK;
+}
+
+nsfr_status nsfr_max_wavespeed(nsfr_ctx* c, const double* U, double* lam) {
+    if (!c || !aligned(U) || !aligned(lam)) return bad("null or misaligned argument");
+    nsfr_status st = use_device(c);
+    if (st) return st;
+    HIP_TRY(launch_max_wavespeed((int64_t)c->E * c->n3, U, c->cfg.gamma, c->red, c->nred, lam, c->stream));
+    return NSFR_OK;
+}
+
+nsfr_status nsfr_cfl_dt(nsfr_ctx* c, const double* U, double cfl, double* dt) {
+    if (!c || !aligned(U) || !aligned(dt) || !(cfl > 0)) return bad("null, misaligned or non-positive argument");
+    nsfr_status st = nsfr_max_wavespeed(c, U, c->red + c->nred - 1);
+    if (st) return st;
+    double dx = (c->cfg.hi - c->cfg.lo) / (c->cfg.ne[0] * (double)c->n);
+    HIP_TRY(launch_cfl_dt(c->red + c->nred - 1, cfl, dx, dt, c->stream));
+    return NSFR_OK;
+}
+
+nsfr_status nsfr_diagnostics(nsfr_ctx* c, const double* U, double t, double* out) {
+    if (!c || !aligned(U) || !aligned(out)) return bad("null or misaligned argument");
+    nsfr_status st = nsfr_residual(c, U, c->wsR, t);
+    if (st) return st;
+    HIP_TRY(launch_diagnostics((int64_t)c->E * c->n3, U, c->wsR, c->cfg.gamma, c->red, c->nred, out, c->stream));
+    return NSFR_OK;
+}
+
+nsfr_status nsfr_kinetic_energy(nsfr_ctx* c, const double* U, double* ke, double* grad) {
+    if (!c || !aligned(U) || !aligned(ke) || (grad && !aligned(grad)) || (const double*)grad == U)
+        return bad("null, misaligned or aliased argument");
+    nsfr_status st = use_device(c);
+    if (st) return st;
+    HIP_TRY(launch_kinetic_energy((int64_t)c->E * c->n3, U, c->invWJ, c->red, c->nred, ke, grad, c->stream));
+    return NSFR_OK;
+}
+
+nsfr_status nsfr_check_state(nsfr_ctx* c, const double* U, int32_t* bad_host) {
+    if (!c || !aligned(U) || !bad_host) return bad("null or misaligned argument");
+    nsfr_status st = use_device(c);
+    if (st) return st;
+    HIP_TRY(launch_check_state((int64_t)c->E * c->n3, U, c->cfg.gamma, c->cnt, c->stream));
+    int32_t h[64];
+    HIP_TRY(hipMemcpyAsync(h, c->cnt, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    int32_t tot = 0;
+    for (int i = 0; i < 64; ++i) tot += h[i];
+    *bad_host = tot;
+    if (tot > 0) {
+        set_error("state has nodes with rho <= 0, p <= 0 or NaN");
+        return NSFR_EUNPHYSICAL;
+    }
+    return NSFR_OK;
+}
+
+nsfr_status nsfr_rhs_vjp(nsfr_ctx* c, const double* U, const double* lam, double* g, double t) {
+    (void)t;   // the source term does not depend on U
+    if (!c || !aligned(U) || !aligned(lam) || !aligned(g) || g == U || g == lam)
+        return bad("null, misaligned or aliased argument");
+    if (c->cfg.surface_diss) {
+        set_error("rhs_vjp supports the entropy-conserving surface flux only (surface_diss = 0)");
+        return NSFR_ENOTSUP;
+    }
+    nsfr_status st = use_device(c);
+    if (st) return st;
+    StageArgs a = base_args(c);
+    a.Uin = U;
+    hipError_t e = launch_vjp(c->p, c->cfg.c_fr != 0.0, c->cfg.flux, a, lam, g, c->wsR2, c->stream);
+    if (e != hipSuccess) {
+        set_error(std::string("vjp kernel launch: ") + hipGetErrorString(e));
+        return NSFR_EHIP;
+    }
+    return NSFR_OK;
+}
+
+nsfr_status nsfr_rk4_step_vjp(nsfr_ctx* c, const double* U, const double* dt, double t, const double* lam_next,
+                              double* lam, double* work) {
+    if (!c || !aligned(U) || !aligned(dt) || !aligned(lam_next) || !aligned(lam) || !aligned(work) || lam == U)
+        return bad("null, misaligned or aliased argument");
+    if (c->cfg.surface_diss) {
+        set_error("rk4_step_vjp supports the entropy-conserving surface flux only (surface_diss = 0)");
+        return NSFR_ENOTSUP;
+    }
+    nsfr_status st = use_device(c);
+    if (st) return st;
+    const int64_t ns = 5 * c->E * (int64_t)c->n3;
+    double* w0 = work;            // copy of lam_next
+    double* Y2 = work + ns;
+    double* Y3 = work + 2 * ns;
+    double* Y4 = work + 3 * ns;
+    double* kap = work + 4 * ns;  // stage derivative, then stage cotangent
+    double* gs = work + 5 * ns;   // VJP of a stage
+    hipStream_t s = c->stream;
+    StageArgs a = base_args(c);
+    // forward recomputation of the stage states (time enters only the source)
+    auto f = [&](const double* Y, double tt, double* out) -> nsfr_status {
+        StageArgs b = a;
+        b.Uin = Y;
+        b.out = out;
+        b.t = tt;
+        b.tdev = nullptr;
+        b.mode = MODE_RHS;
+        return stage(c, b);
+    };
+    auto vjp = [&](const double* Y, const double* k, double* out) -> nsfr_status {
+        StageArgs b = a;
+        b.Uin = Y;
+        hipError_t e = launch_vjp(c->p, c->cfg.c_fr != 0.0, c->cfg.flux, b, k, out, c->wsR2, s);
+        if (e != hipSuccess) {
+            set_error(std::string("vjp kernel launch: ") + hipGetErrorString(e));
+            return NSFR_EHIP;
+        }
+        return NSFR_OK;
+    };
+    // stage times need dt on the host only for the source term
+    double hdt = 0.0;
+    if (c->cfg.source) {
+        HIP_TRY(hipMemcpyAsync(&hdt, dt, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    if ((st = f(U, t, kap))) return st;
+    HIP_TRY(launch_lincomb(ns, Y2, U, 1.0, 0.0, kap, 0.0, 0.5, dt, 0, s));
+    if ((st = f(Y2, t + 0.5 * hdt, kap))) return st;
+    HIP_TRY(launch_lincomb(ns, Y3, U, 1.0, 0.0, kap, 0.0, 0.5, dt, 0, s));
+    if ((st = f(Y3, t + 0.5 * hdt, kap))) return st;
+    HIP_TRY(launch_lincomb(ns, Y4, U, 1.0, 0.0, kap, 0.0, 1.0, dt, 0, s));
+    // reverse sweep: kappa_s = dJ/dk_s, g_s = f'(Y_s)^T kappa_s, lam = lam' + sum g_s
+    HIP_TRY(launch_lincomb(ns, w0, lam_next, 1.0, 0.0, nullptr, 0.0, 0.0, nullptr, 0, s));
+    HIP_TRY(launch_lincomb(ns, kap, w0, 0.0, 1.0 / 6.0, nullptr, 0.0, 0.0, dt, 0, s));
+    if ((st = vjp(Y4, kap, gs))) return st;
+    HIP_TRY(launch_lincomb(ns, lam, w0, 1.0, 0.0, gs, 1.0, 0.0, nullptr, 0, s));
+    HIP_TRY(launch_lincomb(ns, kap, w0, 0.0, 1.0 / 3.0, gs, 0.0, 1.0, dt, 0, s));
+    if ((st = vjp(Y3, kap, gs))) return st;
+    HIP_TRY(launch_lincomb(ns, lam, nullptr, 0.0, 0.0, gs, 1.0, 0.0, nullptr, 1, s));
+    HIP_TRY(launch_lincomb(ns, kap, w0, 0.0, 1.0 / 3.0, gs, 0.0, 0.5, dt, 0, s));
+    if ((st = vjp(Y2, kap, gs))) return st;
+    HIP_TRY(launch_lincomb(ns, lam, nullptr, 0.0, 0.0, gs, 1.0, 0.0, nullptr, 1, s));
+    HIP_TRY(launch_lincomb(ns, kap, w0, 0.0, 1.0 / 6.0, gs, 0.0, 0.5, dt, 0, s));
+    if ((st = vjp(U, kap, gs))) return st;
+    HIP_TRY(launch_lincomb(ns, lam, nullptr, 0.0, 0.0, gs, 1.0, 0.0, nullptr, 1, s));
+    return NSFR_OK;
+}
+
+}  // extern "C"
+
+// exposed to the other translation units of the library
+namespace nsfr {
+nsfr_ctx* ctx_cast(void* p) { return (nsfr_ctx*)p; }
+}

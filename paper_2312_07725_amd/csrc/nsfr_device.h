@@ -1,0 +1,155 @@
+// Device building blocks shared by the NSFR kernels (gfx950, FP64).
+//
+// Paper references: Sec. 2.1 (Euler system, entropy variables), Sec. 3.3
+// (entropy-conserving two-point flux of Chandrashekar in the variables rho, u,
+// beta = rho / (2p); the experiments of Sec. 6 use Ranocha's pressure fix).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nsfr {
+
+constexpr int MAXN = 6;   // p <= 5
+
+// 1D operators of degree p, passed to kernels by value (kernel-argument
+// memory, read through the scalar cache).
+struct Ops {
+    double w[MAXN];            // LGL weights
+    double S1h[MAXN][MAXN];    // (W D - D^T W) / 2: volume block of (Q~ - Q~^T), halved
+    double D[MAXN][MAXN];      // strong derivative D_ij = l_j'(x_i)
+    double pia[MAXN];          // FR projection Pi~ = I - pia pib^T (rank one)
+    double pib[MAXN];
+    double x[MAXN];            // LGL nodes
+};
+
+// Per-node primitive variables used by the two-point flux.
+struct Prim {
+    double rho, u, v, w, p, beta;
+};
+
+// 1/x for x > 0 normal: hardware reciprocal estimate refined by two Newton
+// steps (error well below one ulp of the products that use it).
+__device__ __forceinline__ double rcp_pos(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-x, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+
+__device__ __forceinline__ Prim primitives(double r, double m1, double m2, double m3, double E, double gm1) {
+    Prim q;
+    double ir = rcp_pos(r);
+    q.rho = r;
+    q.u = m1 * ir;
+    q.v = m2 * ir;
+    q.w = m3 * ir;
+    double kin = 0.5 * (m1 * q.u + m2 * q.v + m3 * q.w);
+    q.p = gm1 * (E - kin);
+    q.beta = 0.5 * r * rcp_pos(q.p);
+    return q;
+}
+
+// Threshold on the squared relative jump below which the logarithmic mean
+// uses its series (same switch as the reference implementation).
+constexpr double LN_SWITCH = 1e-4;
+
+// Logarithmic mean (a - b) / (ln a - ln b). Series branch:
+// s / 2 * f / atanh(f) with f = (a - b) / s, u = f^2, and
+// f / atanh(f) = 1 - u/3 - 4u^2/45 - 44u^3/945 - ..., truncated after u^3
+// (relative truncation below 3e-18 for u < 1e-4). Exactly symmetric in (a, b).
+__device__ __forceinline__ double ln_mean(double a, double b) {
+    double s = a + b, d = a - b;
+    double f = d * rcp_pos(s);
+    double u = f * f;
+    if (u < LN_SWITCH) {
+        double q = __builtin_fma(u, __builtin_fma(u, __builtin_fma(u, -44.0 / 945.0, -4.0 / 45.0), -1.0 / 3.0), 1.0);
+        return 0.5 * s * q;
+    }
+    return d / (log(a) - log(b));
+}
+
+// Reciprocal of the logarithmic mean, (ln a - ln b) / (a - b); series branch
+// 2 / s * atanh(f) / f with atanh(f) / f = 1 + u/3 + u^2/5 + u^3/7 + ...
+__device__ __forceinline__ double inv_ln_mean(double a, double b, double rs) {
+    double d = a - b;
+    double f = d * rs;
+    double u = f * f;
+    if (u < LN_SWITCH) {
+        double q = __builtin_fma(u, __builtin_fma(u, __builtin_fma(u, 1.0 / 7.0, 1.0 / 5.0), 1.0 / 3.0), 1.0);
+        return 2.0 * rs * q;
+    }
+    return (log(a) - log(b)) / d;
+}
+
+// Entropy-conserving, kinetic-energy-preserving two-point flux f_s(A, B) . N
+// for the (unnormalised) direction N (Sec. 3.3; Tadmor's condition, Eq. EC
+// flux). VARIANT 0: momentum pressure is the arithmetic mean of p, energy flux
+// completed by Tadmor's condition (Ranocha's pressure fix); VARIANT 1: plain
+// Chandrashekar, pressure rho_avg / (2 beta_avg).
+//
+// Every expression is written so that swapping A and B leaves each rounded
+// operand unchanged or negates both factors of a product, so the result is
+// bitwise symmetric in (A, B) and odd in N even under FMA contraction.
+template <int VARIANT>
+__device__ __forceinline__ void ec_flux(const Prim& A, const Prim& B, double nx, double ny, double nz,
+                                        double c1, double F[5]) {
+    double una = A.u * nx + A.v * ny + A.w * nz;
+    double unb = B.u * nx + B.v * ny + B.w * nz;
+    double un = 0.5 * (una + unb);
+    double rho_ln = ln_mean(A.rho, B.rho);
+    double rsb = rcp_pos(A.beta + B.beta);
+    double ibl = inv_ln_mean(A.beta, B.beta, rsb);
+    double frho = rho_ln * un;
+    double um = 0.5 * (A.u + B.u), vm = 0.5 * (A.v + B.v), wm = 0.5 * (A.w + B.w);
+    F[0] = frho;
+    if (VARIANT == 0) {
+        double pm = 0.5 * (A.p + B.p);
+        F[1] = um * frho + pm * nx;
+        F[2] = vm * frho + pm * ny;
+        F[3] = wm * frho + pm * nz;
+        double uab = A.u * B.u + A.v * B.v + A.w * B.w;
+        double pe = pm * un - 0.25 * (A.p - B.p) * (una - unb);   // = (pa unb + pb una) / 2
+        F[4] = frho * (c1 * ibl + 0.5 * uab) + pe;
+    } else {
+        double ph = 0.5 * (A.rho + B.rho) * rsb;
+        F[1] = um * frho + ph * nx;
+        F[2] = vm * frho + ph * ny;
+        F[3] = wm * frho + ph * nz;
+        double qa = A.u * A.u + A.v * A.v + A.w * A.w;
+        double qb = B.u * B.u + B.v * B.v + B.w * B.w;
+        F[4] = frho * (c1 * ibl - 0.25 * (qa + qb)) + (um * F[1] + vm * F[2] + wm * F[3]);
+    }
+}
+
+// Local Lax-Friedrichs term -|N| lambda_max (UB - UA) / 2 added to the
+// surface flux of the manufactured-solution runs.
+__device__ __forceinline__ void llf_add(const Prim& A, const Prim& B, const double UA[5], const double UB[5],
+                                        double nx, double ny, double nz, double gamma, double F[5]) {
+    double nn = sqrt(nx * nx + ny * ny + nz * nz);
+    double inn = 1.0 / nn;
+    double una = fabs((A.u * nx + A.v * ny + A.w * nz) * inn);
+    double unb = fabs((B.u * nx + B.v * ny + B.w * nz) * inn);
+    double ca = sqrt(gamma * A.p / A.rho), cb = sqrt(gamma * B.p / B.rho);
+    double lam = fmax(una + ca, unb + cb);
+    double k = 0.5 * lam * nn;
+    for (int s = 0; s < 5; ++s) F[s] -= k * (UB[s] - UA[s]);
+}
+
+// Manufactured-solution source q(x, t) of Sec. 6.1.
+__device__ __forceinline__ void mms_source(double x, double y, double z, double t, double gamma, double q[5]) {
+    const double pi = 3.141592653589793238462643383279502884;
+    double c1 = pi / 10.0;
+    double c2 = -pi / 5.0 + pi / 20.0 * (1.0 + 5.0 * gamma);
+    double c3 = pi / 100.0 * (gamma - 1.0);
+    double c4 = pi / 20.0 * (-7.0 + 15.0 * gamma);
+    double c5 = pi / 100.0 * (3.0 * gamma - 2.0);
+    double s = x + y + z - 2.0 * t;
+    double cs = cos(pi * s), s2 = sin(2.0 * pi * s);
+    q[0] = c1 * cs;
+    q[1] = q[2] = q[3] = c2 * cs + c3 * s2;
+    q[4] = c4 * cs + c5 * s2;
+}
+
+}  // namespace nsfr

@@ -1,0 +1,83 @@
+// Host-side internals of libnsfr: context, operator tables, kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/nsfr.h"
+#include "nsfr_device.h"
+
+namespace nsfr {
+
+struct HostOps {
+    int p, n;
+    double x[MAXN], w[MAXN], D[MAXN][MAXN], S1[MAXN][MAXN], d[MAXN];
+    double pia[MAXN], pib[MAXN];
+    double mu, alpha;
+};
+
+void build_ops(int p, double c, Ops& ops, HostOps& h);
+
+// Geometry of one mesh as the kernels see it.
+struct Geo {
+    int nx, ny, nz;
+    int64_t E;
+    const double* Cline;   // [3 dir][3 comp][E][n (position along line)][n^2 (line)]
+    const double* invWJ;   // [E][n^3]
+    const double* X;       // [3][E][n^3]
+};
+
+enum StageMode : int {
+    MODE_RESIDUAL = 0,   // out = R
+    MODE_RHS = 1,        // out = -A R
+    MODE_RK1 = 2,        // acc = Uin + dt/6 k, out = Uin + dt/2 k
+    MODE_RK2 = 3,        // acc += dt/3 k,      out = Un + dt/2 k
+    MODE_RK3 = 4,        // acc += dt/3 k,      out = Un + dt k
+    MODE_RK4 = 5         // out = acc + dt/6 k
+};
+
+struct StageArgs {
+    const double* Uin;
+    const double* Un;
+    double* acc;
+    double* out;
+    const double* dt;      // device scalar (RK modes)
+    const double* tdev;    // device time, or null to use t
+    double t;
+    Geo geo;
+    Ops ops;
+    double gamma, c1;      // c1 = 1 / (2 (gamma - 1))
+    int epb;               // elements per workgroup
+    int mode;
+    int diss, source;
+};
+
+struct FlowDesc;   // ensemble (ensemble.hip)
+
+// launchers (each returns hipSuccess or the launch error)
+hipError_t launch_geometry(int p, const Ops& ops, int nx, int ny, int nz, double lo, double hi, double beta,
+                           double l, double* X, double* Cline, double* invWJ, double* J, hipStream_t s);
+hipError_t launch_stage(int p, bool cwa, int variant, const StageArgs& a, hipStream_t s);
+int default_epb(int p);
+int max_epb(int p);
+hipError_t launch_geometry_export(int p, int64_t E, const double* Cline, double* C, hipStream_t s);
+hipError_t launch_max_wavespeed(int64_t nnodes, const double* U, double gamma, double* partial, int nblk,
+                                double* lam, hipStream_t s);
+hipError_t launch_cfl_dt(const double* lam, double cfl, double dx, double* dt, hipStream_t s);
+hipError_t launch_diagnostics(int64_t nnodes, const double* U, const double* R, double gamma, double* partial,
+                              int nblk, double* out, hipStream_t s);
+hipError_t launch_kinetic_energy(int64_t nn, const double* U, const double* invWJ, double* partial, int nblk,
+                                 double* ke, double* grad, hipStream_t s);
+hipError_t launch_check_state(int64_t nnodes, const double* U, double gamma, int32_t* count, hipStream_t s);
+hipError_t launch_advance_time(double* t, const double* dt, hipStream_t s);
+hipError_t launch_vjp(int p, bool cwa, int variant, const StageArgs& a, const double* lam, double* g,
+                      double* mu_ws, hipStream_t s);
+
+hipError_t launch_lincomb(int64_t n, double* out, const double* z, double ca, double cb, const double* x, double da,
+                          double db, const double* dt, int accumulate, hipStream_t s);
+
+void set_error(const std::string& msg);
+
+}  // namespace nsfr

@@ -1,0 +1,326 @@
+// Fused NSFR right-hand-side / RK4-stage kernel for gfx950.
+//
+// Paper: Eq. NSFR (volume Hadamard term with the hybridised skew-symmetric
+// operator, surface numerical flux), Sec. 5 (sum-factorised Hadamard product:
+// on the tensor-product LGL element the volume-volume block of (Q~ - Q~^T) in
+// direction k is S1 (x) W (x) W, nonzero only between nodes of one k-line;
+// the surface-volume blocks cancel on collocated LGL nodes), Eq. weight-adj
+// ESFR mass (A = Pi~ (W J)^-1 Pi~^T, Pi~ a tensor product of rank-one
+// corrections of the identity), Sec. 6 (classical RK4).
+//
+// Work decomposition: a workgroup owns `epb` elements. Every element has
+// 3 (p+1)^2 lines (p+1)^2 per direction; one thread owns one line. Its line's
+// primitive variables and metric column live in registers, all
+// (p+1) p / 2 node pairs are evaluated once each (pair symmetry), and the two
+// endpoint face fluxes of the line are computed by the same thread, so every
+// face node's surface term belongs to exactly one thread (no atomics; the
+// kernel is deterministic). Partial residuals of the three directions are
+// summed in LDS in a fixed order, then the weight-adjusted inverse and the RK
+// combination run node-parallel.
+#include "nsfr_host.h"
+
+namespace nsfr {
+
+constexpr int STAGE_BLOCK_MAX = 512;
+
+__device__ __forceinline__ int64_t neighbour(int64_t e, int dir, int side, int nx, int ny, int nz) {
+    int ex = (int)(e % nx);
+    int64_t r = e / nx;
+    int ey = (int)(r % ny);
+    int ez = (int)(r / ny);
+    if (dir == 0) ex = (ex + side + nx) % nx;
+    else if (dir == 1) ey = (ey + side + ny) % ny;
+    else ez = (ez + side + nz) % nz;
+    return ex + (int64_t)nx * (ey + (int64_t)ny * ez);
+}
+
+template <int N>
+__device__ __forceinline__ void line_geometry(int dir, int l, int& base, int& stride) {
+    const int t1 = l % N, t2 = l / N;
+    if (dir == 0) { base = N * t1 + N * N * t2; stride = 1; }
+    else if (dir == 1) { base = t1 + N * N * t2; stride = N; }
+    else { base = t1 + N * t2; stride = N * N; }
+}
+
+// One pass of a rank-one line operator x <- x - vec (coef . x) along
+// direction dir for all (element, state, line) of the workgroup, in LDS.
+template <int N>
+__device__ __forceinline__ void line_pass(double* lr, int epb, int dir, const double* coef, const double* vec) {
+    constexpr int N2 = N * N, N3 = N2 * N;
+    for (int it = threadIdx.x; it < epb * 5 * N2; it += blockDim.x) {
+        int l = it % N2;
+        int sl = it / N2;   // element * 5 + state
+        int base, stride;
+        line_geometry<N>(dir, l, base, stride);
+        double* x = lr + sl * N3 + base;
+        double v[N];
+        double t = 0.0;
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+            v[a] = x[a * stride];
+            t += coef[a] * v[a];
+        }
+#pragma unroll
+        for (int a = 0; a < N; ++a) x[a * stride] = v[a] - vec[a] * t;
+    }
+}
+
+template <int P, bool CWA, int VARIANT>
+__global__ __launch_bounds__(STAGE_BLOCK_MAX) void stage_kernel(StageArgs A) {
+    constexpr int N = P + 1, N2 = N * N, N3 = N2 * N, LINES = 3 * N2;
+    extern __shared__ double lds[];
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int epb = A.epb;
+    const int64_t E = A.geo.E;
+    const int64_t e0 = (int64_t)blockIdx.x * epb;
+    const int64_t SE = E * N3;   // state stride
+    const double gm1 = A.gamma - 1.0;
+    const double c1 = A.c1;
+
+    // ---- 1. primitives of the workgroup's elements -> LDS [epb][6][N3]
+    for (int idx = tid; idx < epb * N3; idx += nth) {
+        int el = idx / N3, node = idx - el * N3;
+        int64_t e = e0 + el;
+        if (e < E) {
+            const double* U = A.Uin + e * N3 + node;
+            Prim q = primitives(U[0], U[SE], U[2 * SE], U[3 * SE], U[4 * SE], gm1);
+            double* L = lds + el * 6 * N3 + node;
+            L[0] = q.rho;
+            L[N3] = q.u;
+            L[2 * N3] = q.v;
+            L[3 * N3] = q.w;
+            L[4 * N3] = q.p;
+            L[5 * N3] = q.beta;
+        }
+    }
+    __syncthreads();
+
+    // ---- 2. line ownership and register loads
+    const bool lt = tid < epb * LINES;
+    const int el = lt ? tid / LINES : 0;
+    const int rem = tid - el * LINES;
+    const int dir = rem / N2;
+    const int l = rem - dir * N2;
+    const int64_t e = e0 + el;
+    const bool active = lt && (e < E);
+    int base, stride;
+    line_geometry<N>(dir, l, base, stride);
+
+    Prim q[N];
+    double cx[N], cy[N], cz[N];
+    if (active) {
+        const double* L = lds + el * 6 * N3;
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+            int node = base + a * stride;
+            q[a].rho = L[node];
+            q[a].u = L[N3 + node];
+            q[a].v = L[2 * N3 + node];
+            q[a].w = L[3 * N3 + node];
+            q[a].p = L[4 * N3 + node];
+            q[a].beta = L[5 * N3 + node];
+        }
+        const double* Cl = A.geo.Cline + ((int64_t)(dir * 3) * E + e) * N3 + l;
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+            cx[a] = Cl[a * N2];
+            cy[a] = Cl[SE + a * N2];
+            cz[a] = Cl[2 * SE + a * N2];
+        }
+    }
+    __syncthreads();   // the primitive block is dead from here on
+
+    // ---- 3. line residual: volume pairs, then the two endpoint face fluxes
+    double R[5][N];
+#pragma unroll
+    for (int s = 0; s < 5; ++s)
+#pragma unroll
+        for (int a = 0; a < N; ++a) R[s][a] = 0.0;
+    if (active) {
+#pragma unroll
+        for (int a = 0; a < N - 1; ++a) {
+#pragma unroll
+            for (int b = a + 1; b < N; ++b) {
+                double F[5];
+                // direction C(a) + C(b) = 2 N; the 1/2 is folded into S1h
+                ec_flux<VARIANT>(q[a], q[b], cx[a] + cx[b], cy[a] + cy[b], cz[a] + cz[b], c1, F);
+                const double sab = A.ops.S1h[a][b];
+#pragma unroll
+                for (int s = 0; s < 5; ++s) {
+                    R[s][a] = __builtin_fma(sab, F[s], R[s][a]);
+                    R[s][b] = __builtin_fma(-sab, F[s], R[s][b]);
+                }
+            }
+        }
+        // face neighbours across the two ends of this line (periodic box)
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const int aown = side ? N - 1 : 0;
+            const int anbr = side ? 0 : N - 1;
+            const double sg = side ? 0.5 : -0.5;   // outward reference normal / 2
+            const int64_t en = neighbour(e, dir, side ? 1 : -1, A.geo.nx, A.geo.ny, A.geo.nz);
+            const double* Cn = A.geo.Cline + ((int64_t)(dir * 3) * E + en) * N3 + anbr * N2 + l;
+            const double* Ub = A.Uin + en * N3 + base + anbr * stride;
+            double Un5[5];
+#pragma unroll
+            for (int s = 0; s < 5; ++s) Un5[s] = Ub[s * SE];
+            Prim qn = primitives(Un5[0], Un5[1], Un5[2], Un5[3], Un5[4], gm1);
+            double nx = sg * (cx[aown] + Cn[0]), ny = sg * (cy[aown] + Cn[SE]), nz = sg * (cz[aown] + Cn[2 * SE]);
+            double F[5];
+            ec_flux<VARIANT>(q[aown], qn, nx, ny, nz, c1, F);
+            if (A.diss) {
+                const double* Uo = A.Uin + e * N3 + base + aown * stride;
+                double Uo5[5];
+#pragma unroll
+                for (int s = 0; s < 5; ++s) Uo5[s] = Uo[s * SE];
+                llf_add(q[aown], qn, Uo5, Un5, nx, ny, nz, A.gamma, F);
+            }
+#pragma unroll
+            for (int s = 0; s < 5; ++s) R[s][aown] += F[s];
+        }
+    }
+
+    // ---- 4. sum the three directions in LDS ([epb][5][N3]), fixed order
+    double* lr = lds;
+    const double wperp = A.ops.w[l % N] * A.ops.w[l / N];
+    for (int ph = 0; ph < 3; ++ph) {
+        if (active && dir == ph) {
+            double* x = lr + el * 5 * N3 + base;
+#pragma unroll
+            for (int s = 0; s < 5; ++s)
+#pragma unroll
+                for (int a = 0; a < N; ++a) {
+                    double v = R[s][a] * wperp;
+                    if (ph == 0) x[s * N3 + a * stride] = v;
+                    else x[s * N3 + a * stride] += v;
+                }
+        }
+        __syncthreads();
+    }
+
+    // ---- 5. source, mass inverse, RK combination (node-parallel)
+    const int mode = A.mode;
+    double dt = 0.0, cstage = 0.0;
+    if (mode >= MODE_RK1) {
+        dt = *A.dt;
+        cstage = (mode == MODE_RK1) ? 0.0 : (mode == MODE_RK4 ? 1.0 : 0.5);
+    }
+    if (A.source) {
+        const double t = (A.tdev ? *A.tdev : A.t) + cstage * dt;
+        for (int idx = tid; idx < epb * N3; idx += nth) {
+            int eli = idx / N3, node = idx - eli * N3;
+            int64_t ee = e0 + eli;
+            if (ee < E) {
+                double qs[5];
+                const double* X = A.geo.X + ee * N3 + node;
+                mms_source(X[0], X[SE], X[2 * SE], t, A.gamma, qs);
+                double wj = 1.0 / A.geo.invWJ[ee * N3 + node];
+                double* x = lr + eli * 5 * N3 + node;
+#pragma unroll
+                for (int s = 0; s < 5; ++s) x[s * N3] -= wj * qs[s];
+            }
+        }
+        __syncthreads();
+    }
+    if (mode == MODE_RESIDUAL) {
+        for (int idx = tid; idx < epb * N3; idx += nth) {
+            int eli = idx / N3, node = idx - eli * N3;
+            int64_t ee = e0 + eli;
+            if (ee < E) {
+#pragma unroll
+                for (int s = 0; s < 5; ++s) A.out[s * SE + ee * N3 + node] = lr[(eli * 5 + s) * N3 + node];
+            }
+        }
+        return;
+    }
+    if (CWA) {
+        for (int d = 0; d < 3; ++d) {   // Pi~^T along xi, eta, zeta
+            line_pass<N>(lr, epb, d, A.ops.pia, A.ops.pib);
+            __syncthreads();
+        }
+        for (int idx = tid; idx < epb * N3; idx += nth) {
+            int eli = idx / N3, node = idx - eli * N3;
+            int64_t ee = e0 + eli;
+            double iw = (ee < E) ? A.geo.invWJ[ee * N3 + node] : 0.0;
+#pragma unroll
+            for (int s = 0; s < 5; ++s) lr[(eli * 5 + s) * N3 + node] *= iw;
+        }
+        __syncthreads();
+        for (int d = 0; d < 3; ++d) {   // Pi~ along xi, eta, zeta
+            line_pass<N>(lr, epb, d, A.ops.pib, A.ops.pia);
+            __syncthreads();
+        }
+    }
+    for (int idx = tid; idx < epb * N3; idx += nth) {
+        int eli = idx / N3, node = idx - eli * N3;
+        int64_t ee = e0 + eli;
+        if (ee >= E) continue;
+        const int64_t g = ee * N3 + node;
+        const double iw = CWA ? 1.0 : A.geo.invWJ[g];
+#pragma unroll
+        for (int s = 0; s < 5; ++s) {
+            const double k = -(lr[(eli * 5 + s) * N3 + node] * iw);
+            const int64_t gi = s * SE + g;
+            switch (mode) {
+                case MODE_RHS: A.out[gi] = k; break;
+                case MODE_RK1: {
+                    double u = A.Uin[gi];
+                    A.acc[gi] = __builtin_fma(dt / 6.0, k, u);
+                    A.out[gi] = __builtin_fma(0.5 * dt, k, u);
+                } break;
+                case MODE_RK2: {
+                    A.acc[gi] = __builtin_fma(dt / 3.0, k, A.acc[gi]);
+                    A.out[gi] = __builtin_fma(0.5 * dt, k, A.Un[gi]);
+                } break;
+                case MODE_RK3: {
+                    A.acc[gi] = __builtin_fma(dt / 3.0, k, A.acc[gi]);
+                    A.out[gi] = __builtin_fma(dt, k, A.Un[gi]);
+                } break;
+                default: A.out[gi] = __builtin_fma(dt / 6.0, k, A.acc[gi]); break;
+            }
+        }
+    }
+}
+
+int max_epb(int p) {
+    int lines = 3 * (p + 1) * (p + 1);
+    return STAGE_BLOCK_MAX / lines;
+}
+
+int default_epb(int p) {
+    switch (p) {
+        case 2: return 16;
+        case 3: return 8;
+        case 4: return 5;
+        default: return 4;
+    }
+}
+
+template <int P, bool CWA, int V>
+static hipError_t launch_t(const StageArgs& a, hipStream_t s) {
+    constexpr int N = P + 1, N3 = N * N * N, LINES = 3 * N * N;
+    int threads = ((a.epb * LINES + 63) / 64) * 64;
+    size_t lds = (size_t)a.epb * 6 * N3 * sizeof(double);
+    unsigned blocks = (unsigned)((a.geo.E + a.epb - 1) / a.epb);
+    stage_kernel<P, CWA, V><<<blocks, threads, lds, s>>>(a);
+    return hipGetLastError();
+}
+
+template <int P>
+static hipError_t launch_p(bool cwa, int v, const StageArgs& a, hipStream_t s) {
+    if (cwa) return v ? launch_t<P, true, 1>(a, s) : launch_t<P, true, 0>(a, s);
+    return v ? launch_t<P, false, 1>(a, s) : launch_t<P, false, 0>(a, s);
+}
+
+hipError_t launch_stage(int p, bool cwa, int variant, const StageArgs& a, hipStream_t s) {
+    if (a.epb < 1 || a.epb > max_epb(p)) return hipErrorInvalidValue;
+    switch (p) {
+        case 2: return launch_p<2>(cwa, variant, a, s);
+        case 3: return launch_p<3>(cwa, variant, a, s);
+        case 4: return launch_p<4>(cwa, variant, a, s);
+        case 5: return launch_p<5>(cwa, variant, a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace nsfr
