@@ -119,6 +119,8 @@ def main():
     ap.add_argument("--ne", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="skip the extra p / adjoint measurements")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one plain elementwise copy of 2 x 1 GiB (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -128,6 +130,12 @@ def main():
         sys.exit(1)
 
     from paper_2312_07725_amd import nsfr, inputs
+    if args.calibrate_copy:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.add(src, 0.0, out=dst)   # reads 1 GiB, writes 1 GiB
+        torch.cuda.synchronize()
+        del src, dst
     p, ne = args.p, args.ne
     c = nsfr.c_hu(p)
     g = nsfr.NSFR(p, ne, beta=0.2, c=c)

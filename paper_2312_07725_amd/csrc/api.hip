@@ -466,7 +466,9 @@ nsfr_status nsfr_rk4_step_vjp(nsfr_ctx* c, const double* U, const double* dt, do
 
 }  // extern "C"
 
-// exposed to the other translation units of the library
+// exposed to the other translation units of the library (ensembles)
 namespace nsfr {
-nsfr_ctx* ctx_cast(void* p) { return (nsfr_ctx*)p; }
-}
+StageArgs ctx_stage_args(const nsfr_ctx* c) { return base_args(c); }
+int ctx_kind(const nsfr_ctx* c) { return kind_code(c->p, c->cfg.c_fr != 0.0, c->cfg.flux); }
+int64_t ctx_state_size(const nsfr_ctx* c) { return 5 * c->E * (int64_t)c->n3; }
+}  // namespace nsfr

@@ -80,4 +80,12 @@ hipError_t launch_lincomb(int64_t n, double* out, const double* z, double ca, do
 
 void set_error(const std::string& msg);
 
+// kernel variant code used by the ensemble dispatcher
+constexpr int kind_code(int p, bool cwa, int variant) { return (p - 2) * 4 + (cwa ? 2 : 0) + variant; }
+StageArgs ctx_stage_args(const nsfr_ctx* c);
+int ctx_kind(const nsfr_ctx* c);
+int64_t ctx_state_size(const nsfr_ctx* c);
+hipError_t launch_ensemble_stage(const StageArgs* table, const int2* items, int nitems, const int* kinds,
+                                 size_t lds_bytes, int grid, hipStream_t s);
+
 }  // namespace nsfr

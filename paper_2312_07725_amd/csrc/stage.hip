@@ -65,14 +65,13 @@ __device__ __forceinline__ void line_pass(double* lr, int epb, int dir, const do
     }
 }
 
+// The whole stage for the `epb` elements starting at e0 (one workgroup).
 template <int P, bool CWA, int VARIANT>
-__global__ __launch_bounds__(STAGE_BLOCK_MAX) void stage_kernel(StageArgs A) {
+__device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0, double* lds) {
     constexpr int N = P + 1, N2 = N * N, N3 = N2 * N, LINES = 3 * N2;
-    extern __shared__ double lds[];
     const int tid = threadIdx.x, nth = blockDim.x;
     const int epb = A.epb;
     const int64_t E = A.geo.E;
-    const int64_t e0 = (int64_t)blockIdx.x * epb;
     const int64_t SE = E * N3;   // state stride
     const double gm1 = A.gamma - 1.0;
     const double c1 = A.c1;
@@ -280,6 +279,45 @@ __global__ __launch_bounds__(STAGE_BLOCK_MAX) void stage_kernel(StageArgs A) {
             }
         }
     }
+}
+
+template <int P, bool CWA, int VARIANT>
+__global__ __launch_bounds__(STAGE_BLOCK_MAX) void stage_kernel(StageArgs A) {
+    extern __shared__ double lds[];
+    stage_body<P, CWA, VARIANT>(A, (int64_t)blockIdx.x * A.epb, lds);
+}
+
+// Persistent ensemble kernel: every workgroup walks the work list (flow,
+// first element) with a static stride, so the assignment is deterministic;
+// the list is sorted by decreasing cost. The variant of the body is chosen
+// per item from the flow's kind code (uniform across the workgroup).
+__global__ __launch_bounds__(STAGE_BLOCK_MAX) void ensemble_kernel(const StageArgs* __restrict__ table,
+                                                                   const int2* __restrict__ items, int nitems,
+                                                                   const int* __restrict__ kinds) {
+    extern __shared__ double lds[];
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        __syncthreads();   // the previous item's LDS reads are complete
+        const int2 w = items[it];
+        const int f = __builtin_amdgcn_readfirstlane(w.x);
+        const int64_t e0 = __builtin_amdgcn_readfirstlane(w.y);
+        const StageArgs& A = table[f];
+        switch (__builtin_amdgcn_readfirstlane(kinds[f])) {
+#define NSFR_CASE(P, C, V) \
+    case kind_code(P, C, V): stage_body<P, C, V>(A, e0, lds); break;
+            NSFR_CASE(2, false, 0) NSFR_CASE(2, false, 1) NSFR_CASE(2, true, 0) NSFR_CASE(2, true, 1)
+            NSFR_CASE(3, false, 0) NSFR_CASE(3, false, 1) NSFR_CASE(3, true, 0) NSFR_CASE(3, true, 1)
+            NSFR_CASE(4, false, 0) NSFR_CASE(4, false, 1) NSFR_CASE(4, true, 0) NSFR_CASE(4, true, 1)
+            NSFR_CASE(5, false, 0) NSFR_CASE(5, false, 1) NSFR_CASE(5, true, 0) NSFR_CASE(5, true, 1)
+#undef NSFR_CASE
+            default: break;
+        }
+    }
+}
+
+hipError_t launch_ensemble_stage(const StageArgs* table, const int2* items, int nitems, const int* kinds,
+                                 size_t lds_bytes, int grid, hipStream_t s) {
+    ensemble_kernel<<<grid, STAGE_BLOCK_MAX, lds_bytes, s>>>(table, items, nitems, kinds);
+    return hipGetLastError();
 }
 
 int max_epb(int p) {

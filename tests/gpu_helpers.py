@@ -50,5 +50,22 @@ def assert_parity(got, ref, tol, what=""):
     return e
 
 
+def assert_parity_scaled(got, ref, scale, tol, what=""):
+    """Element-by-element parity in the normwise sense: per state,
+    max_i |got_i - ref_i| / max_i scale_i <= tol, where scale_i is the sum of
+    the magnitudes of the terms that produce entry i (oracle residual_scale /
+    rhs_scale). Returns the per-state errors; the message also reports the
+    plain max-normalised errors."""
+    got = got.detach().double().cpu()
+    ref = ref.detach().double().cpu()
+    scale = scale.detach().double().cpu()
+    S = ref.shape[0]
+    d = (got - ref).abs().reshape(S, -1).amax(1)
+    e = d / scale.reshape(S, -1).amax(1).clamp_min(1e-300)
+    assert bool((e <= tol).all()), (f"{what}: per-state scaled errors {e.tolist()} exceed {tol} "
+                                    f"(max-normalised {rel_err(got, ref).tolist()})")
+    return e
+
+
 def cuda(t):
     return t.to("cuda").contiguous()

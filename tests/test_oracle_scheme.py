@@ -233,3 +233,14 @@ def test_mms_order_of_accuracy():
         errs.append(float(err[0]))
     rate = math.log2(errs[0] / errs[1])
     assert rate > p + 0.8, (errs, rate)
+
+
+@pytest.mark.parametrize("diss", [False, True])
+def test_residual_scale_bounds_residual(diss):
+    """The round-off scale is a sum of term magnitudes, so it bounds |R| and
+    |A R| entry by entry (triangle inequality)."""
+    s = oracle.Scheme(3, (2, 2, 3), beta=0.2, c=1e-3, dissipation=diss)
+    U = inputs.perturbed_state(s.X, seed=4)
+    R = s.residual(U)
+    assert bool((R.abs() <= s.residual_scale(U) * (1 + 1e-12)).all())
+    assert bool((s.rhs(U).abs() <= s.rhs_scale(U) * (1 + 1e-12)).all())
