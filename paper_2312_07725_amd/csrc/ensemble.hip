@@ -24,10 +24,7 @@ constexpr int ENS_BLOCK = 512;
 
 int mode_slot(int mode) { return mode == MODE_RHS ? 4 : mode - MODE_RK1; }
 
-int default_ens_epb(int p) {   // fill a 512-thread workgroup
-    int lines = 3 * (p + 1) * (p + 1);
-    return ENS_BLOCK / lines;
-}
+int default_ens_epb(int p) { return max_epb(p); }
 }  // namespace
 
 struct nsfr_ens {
@@ -88,7 +85,7 @@ static nsfr_status build_items(nsfr_ens* s) {
             int cnt = (int)std::min<int64_t>(epb, E - e0);
             items.push_back({f, (int)e0, cnt * n3 * per_node_pairs});
         }
-        lds = std::max(lds, (size_t)epb * 6 * n3 * sizeof(double));
+        lds = std::max(lds, (size_t)epb * 15 * n3 * sizeof(double));
     }
     std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) { return a.cost > b.cost; });
     std::vector<int2> h(items.size());
@@ -246,8 +243,8 @@ nsfr_status nsfr_ens_set_tile(nsfr_ens* s, int32_t p, int32_t epb) {
         return NSFR_EINVAL;
     }
     if (epb == 0) epb = default_ens_epb(p);
-    if (epb < 1 || epb * 3 * (p + 1) * (p + 1) > ENS_BLOCK) {
-        set_error("tile does not fit a 512-thread workgroup");
+    if (epb < 1 || epb > max_epb(p)) {
+        set_error("tile does not fit a 512-thread workgroup or the LDS budget");
         return NSFR_EINVAL;
     }
     s->epb[p - 2] = epb;

@@ -65,10 +65,29 @@ __device__ __forceinline__ void line_pass(double* lr, int epb, int dir, const do
     }
 }
 
+// Primitive variables of a node from the LDS block [6][N3].
+template <int N3>
+__device__ __forceinline__ Prim lds_prim(const double* L, int node) {
+    Prim q;
+    q.rho = L[node];
+    q.u = L[N3 + node];
+    q.v = L[2 * N3 + node];
+    q.w = L[3 * N3 + node];
+    q.p = L[4 * N3 + node];
+    q.beta = L[5 * N3 + node];
+    return q;
+}
+
 // The whole stage for the `epb` elements starting at e0 (one workgroup).
+//
+// LDS per element: primitives [6][N3] and the metric columns of the three
+// directions in line-major order [dir][comp][position][line] (9 N3 doubles);
+// after the pair sweep the primitive block is reused for the residual
+// accumulator [5][N3]. Line data are read from LDS inside the pair loop, so a
+// thread keeps only the residual of its line in registers.
 template <int P, bool CWA, int VARIANT>
 __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0, double* lds) {
-    constexpr int N = P + 1, N2 = N * N, N3 = N2 * N, LINES = 3 * N2;
+    constexpr int N = P + 1, N2 = N * N, N3 = N2 * N, LINES = 3 * N2, LDSE = 15 * N3;
     const int tid = threadIdx.x, nth = blockDim.x;
     const int epb = A.epb;
     const int64_t E = A.geo.E;
@@ -76,25 +95,28 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
     const double gm1 = A.gamma - 1.0;
     const double c1 = A.c1;
 
-    // ---- 1. primitives of the workgroup's elements -> LDS [epb][6][N3]
+    // ---- 1. primitives and metric columns of the workgroup's elements -> LDS
     for (int idx = tid; idx < epb * N3; idx += nth) {
         int el = idx / N3, node = idx - el * N3;
         int64_t e = e0 + el;
         if (e < E) {
             const double* U = A.Uin + e * N3 + node;
             Prim q = primitives(U[0], U[SE], U[2 * SE], U[3 * SE], U[4 * SE], gm1);
-            double* L = lds + el * 6 * N3 + node;
+            double* L = lds + el * LDSE + node;
             L[0] = q.rho;
             L[N3] = q.u;
             L[2 * N3] = q.v;
             L[3 * N3] = q.w;
             L[4 * N3] = q.p;
             L[5 * N3] = q.beta;
+            const double* Cg = A.geo.Cline + e * N3 + node;   // same offset in line-major order
+#pragma unroll
+            for (int k = 0; k < 9; ++k) L[(6 + k) * N3] = Cg[k * SE];
         }
     }
     __syncthreads();
 
-    // ---- 2. line ownership and register loads
+    // ---- 2. line ownership
     const bool lt = tid < epb * LINES;
     const int el = lt ? tid / LINES : 0;
     const int rem = tid - el * LINES;
@@ -104,30 +126,8 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
     const bool active = lt && (e < E);
     int base, stride;
     line_geometry<N>(dir, l, base, stride);
-
-    Prim q[N];
-    double cx[N], cy[N], cz[N];
-    if (active) {
-        const double* L = lds + el * 6 * N3;
-#pragma unroll
-        for (int a = 0; a < N; ++a) {
-            int node = base + a * stride;
-            q[a].rho = L[node];
-            q[a].u = L[N3 + node];
-            q[a].v = L[2 * N3 + node];
-            q[a].w = L[3 * N3 + node];
-            q[a].p = L[4 * N3 + node];
-            q[a].beta = L[5 * N3 + node];
-        }
-        const double* Cl = A.geo.Cline + ((int64_t)(dir * 3) * E + e) * N3 + l;
-#pragma unroll
-        for (int a = 0; a < N; ++a) {
-            cx[a] = Cl[a * N2];
-            cy[a] = Cl[SE + a * N2];
-            cz[a] = Cl[2 * SE + a * N2];
-        }
-    }
-    __syncthreads();   // the primitive block is dead from here on
+    const double* Lp = lds + el * LDSE;                      // primitives
+    const double* Lc = lds + el * LDSE + (6 + 3 * dir) * N3 + l;   // metric column, [comp][pos][line]
 
     // ---- 3. line residual: volume pairs, then the two endpoint face fluxes
     double R[5][N];
@@ -138,11 +138,15 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
     if (active) {
 #pragma unroll
         for (int a = 0; a < N - 1; ++a) {
+            const Prim qa = lds_prim<N3>(Lp, base + a * stride);
+            const double cax = Lc[a * N2], cay = Lc[N3 + a * N2], caz = Lc[2 * N3 + a * N2];
 #pragma unroll
             for (int b = a + 1; b < N; ++b) {
+                const Prim qb = lds_prim<N3>(Lp, base + b * stride);
+                const double cbx = Lc[b * N2], cby = Lc[N3 + b * N2], cbz = Lc[2 * N3 + b * N2];
                 double F[5];
                 // direction C(a) + C(b) = 2 N; the 1/2 is folded into S1h
-                ec_flux<VARIANT>(q[a], q[b], cx[a] + cx[b], cy[a] + cy[b], cz[a] + cz[b], c1, F);
+                ec_flux<VARIANT>(qa, qb, cax + cbx, cay + cby, caz + cbz, c1, F);
                 const double sab = A.ops.S1h[a][b];
 #pragma unroll
                 for (int s = 0; s < 5; ++s) {
@@ -163,23 +167,28 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
             double Un5[5];
 #pragma unroll
             for (int s = 0; s < 5; ++s) Un5[s] = Ub[s * SE];
-            Prim qn = primitives(Un5[0], Un5[1], Un5[2], Un5[3], Un5[4], gm1);
-            double nx = sg * (cx[aown] + Cn[0]), ny = sg * (cy[aown] + Cn[SE]), nz = sg * (cz[aown] + Cn[2 * SE]);
+            const double cnx = Cn[0], cny = Cn[SE], cnz = Cn[2 * SE];
+            const Prim qn = primitives(Un5[0], Un5[1], Un5[2], Un5[3], Un5[4], gm1);
+            const Prim qo = lds_prim<N3>(Lp, base + aown * stride);
+            const double nx = sg * (Lc[aown * N2] + cnx), ny = sg * (Lc[N3 + aown * N2] + cny),
+                         nz = sg * (Lc[2 * N3 + aown * N2] + cnz);
             double F[5];
-            ec_flux<VARIANT>(q[aown], qn, nx, ny, nz, c1, F);
+            ec_flux<VARIANT>(qo, qn, nx, ny, nz, c1, F);
             if (A.diss) {
                 const double* Uo = A.Uin + e * N3 + base + aown * stride;
                 double Uo5[5];
 #pragma unroll
                 for (int s = 0; s < 5; ++s) Uo5[s] = Uo[s * SE];
-                llf_add(q[aown], qn, Uo5, Un5, nx, ny, nz, A.gamma, F);
+                llf_add(qo, qn, Uo5, Un5, nx, ny, nz, A.gamma, F);
             }
 #pragma unroll
             for (int s = 0; s < 5; ++s) R[s][aown] += F[s];
         }
     }
+    __syncthreads();   // all LDS line reads are done; the primitive block becomes the accumulator
 
-    // ---- 4. sum the three directions in LDS ([epb][5][N3]), fixed order
+    // ---- 4. sum the three directions in LDS ([epb][5][N3] at the element's
+    //         block start), fixed order
     double* lr = lds;
     const double wperp = A.ops.w[l % N] * A.ops.w[l / N];
     for (int ph = 0; ph < 3; ++ph) {
@@ -281,10 +290,21 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
     }
 }
 
+// Workgroups are dispatched to the 8 XCDs round-robin; remap the workgroup
+// index so that each XCD processes one contiguous range of elements, which
+// keeps most face-neighbour reads inside that XCD's L2.
+__device__ __forceinline__ int xcd_remap(int g, int nb) {
+    constexpr int NX = 8;
+    const int q = nb / NX, r = nb % NX;
+    const int x = g % NX, k = g / NX;
+    return (x < r) ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
 template <int P, bool CWA, int VARIANT>
 __global__ __launch_bounds__(STAGE_BLOCK_MAX) void stage_kernel(StageArgs A) {
     extern __shared__ double lds[];
-    stage_body<P, CWA, VARIANT>(A, (int64_t)blockIdx.x * A.epb, lds);
+    const int g = xcd_remap(blockIdx.x, gridDim.x);
+    stage_body<P, CWA, VARIANT>(A, (int64_t)g * A.epb, lds);
 }
 
 // Persistent ensemble kernel: every workgroup walks the work list (flow,
@@ -320,17 +340,22 @@ hipError_t launch_ensemble_stage(const StageArgs* table, const int2* items, int 
     return hipGetLastError();
 }
 
+// LDS per element of the stage kernel (doubles): primitives + metric columns
+constexpr int stage_lds_doubles(int n3) { return 15 * n3; }
+
 int max_epb(int p) {
-    int lines = 3 * (p + 1) * (p + 1);
-    return STAGE_BLOCK_MAX / lines;
+    const int n = p + 1, lines = 3 * n * n, n3 = n * n * n;
+    const int by_threads = STAGE_BLOCK_MAX / lines;
+    const int by_lds = (int)(65536 / (stage_lds_doubles(n3) * sizeof(double)));
+    return by_threads < by_lds ? by_threads : by_lds;
 }
 
 int default_epb(int p) {
     switch (p) {
         case 2: return 16;
-        case 3: return 8;
-        case 4: return 5;
-        default: return 4;
+        case 3: return 4;
+        case 4: return 4;
+        default: return 2;
     }
 }
 
@@ -338,7 +363,7 @@ template <int P, bool CWA, int V>
 static hipError_t launch_t(const StageArgs& a, hipStream_t s) {
     constexpr int N = P + 1, N3 = N * N * N, LINES = 3 * N * N;
     int threads = ((a.epb * LINES + 63) / 64) * 64;
-    size_t lds = (size_t)a.epb * 6 * N3 * sizeof(double);
+    size_t lds = (size_t)a.epb * stage_lds_doubles(N3) * sizeof(double);
     unsigned blocks = (unsigned)((a.geo.E + a.epb - 1) / a.epb);
     stage_kernel<P, CWA, V><<<blocks, threads, lds, s>>>(a);
     return hipGetLastError();

@@ -120,6 +120,9 @@ class NSFR:
                  source=0, tile=0):
         if not torch.cuda.is_available():
             raise RuntimeError("libnsfr needs a HIP GPU; none is visible")
+        if not tile:
+            from .tune import load_tiles
+            tile = load_tiles().get(int(p), 0)
         self.cfg = make_config(p, ne, lo, hi, beta, l, gamma, c, flux, diss, source, tile)
         self.p, self.n = int(p), int(p) + 1
         self.gamma = float(gamma)
@@ -277,6 +280,10 @@ class Ensemble:
         _check(_lib().nsfr_ens_create(arr, len(self.configs), _stream(), byref(self._h)), "nsfr_ens_create")
         offs = (c_int64 * (len(self.configs) + 1))()
         _check(_lib().nsfr_ens_offsets(self._h, offs), "nsfr_ens_offsets")
+        from .tune import load_tiles
+        for p, epb in load_tiles().items():
+            if _lib().nsfr_ens_set_tile(self._h, int(p), int(epb)) != NSFR_OK:
+                _lib().nsfr_ens_set_tile(self._h, int(p), 0)
         self.offsets = [int(v) for v in offs]
         self.total = self.offsets[-1]
 

@@ -1,0 +1,92 @@
+"""Autotuner for the stage-kernel tile (elements per workgroup) per degree.
+
+    python -m paper_2312_07725_amd.tune [--ne 16] [--reps 200] [--out PATH]
+
+For every p in 2..5 it times the full right-hand side (nsfr_rhs: volume and
+surface fluxes, weight-adjusted inverse with c = c_HU) of the warped TGV on an
+ne^3 mesh for every tile the library accepts, and writes the fastest tile per
+degree to tiles_gfx950.json next to this file. NSFR(tile=0) and Ensemble read
+that table. Timing uses HIP events on the current stream, median of 5 batches.
+"""
+import argparse
+import json
+import os
+import statistics
+import sys
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TILES_PATH = os.path.join(HERE, "tiles_gfx950.json")
+
+
+def load_tiles(path=TILES_PATH):
+    """{p: epb} from the tuned table, or {} if there is none."""
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+        return {int(k): int(v["epb"]) for k, v in d.get("tiles", {}).items()}
+    except (OSError, ValueError, KeyError):
+        return {}
+
+
+def time_rhs(g, U, out, reps):
+    st = torch.cuda.current_stream()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(10):
+        g.rhs(U, out)
+    times = []
+    for _ in range(5):
+        torch.cuda.synchronize()
+        s.record(st)
+        for _ in range(reps):
+            g.rhs(U, out)
+        e.record(st)
+        torch.cuda.synchronize()
+        times.append(s.elapsed_time(e) * 1e3 / reps)
+    return statistics.median(times)
+
+
+def tune(ne=16, reps=200, ps=(2, 3, 4, 5), out=TILES_PATH, verbose=True):
+    from . import inputs
+    from .nsfr import NSFR, NSFRError, c_hu
+    table = {}
+    for p in ps:
+        res = {}
+        X = None
+        for epb in range(1, 33):
+            try:
+                g = NSFR(p, ne, beta=0.2, c=c_hu(p), tile=epb)
+            except NSFRError:
+                continue
+            if X is None:
+                X = g.node_coords().cpu()
+                U = inputs.tgv_state(X).cuda().contiguous()
+            o = g.empty()
+            res[epb] = time_rhs(g, U, o, reps)
+            if verbose:
+                print(f"p={p} epb={epb}: {res[epb]:.2f} us", flush=True)
+            del g, o
+        best = min(res, key=res.get)
+        table[str(p)] = {"epb": best, "rhs_us": res[best], "all_us": {str(k): v for k, v in res.items()}}
+    doc = {"device": torch.cuda.get_device_name(0), "mesh": f"{ne}^3 warped TGV (beta=0.2), c=c_HU",
+           "metric": "median time of one nsfr_rhs (us)", "tiles": table}
+    if out:
+        with open(out, "w") as fh:
+            json.dump(doc, fh, indent=1)
+    return doc
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--ne", type=int, default=16)
+    ap.add_argument("--reps", type=int, default=200)
+    ap.add_argument("--out", default=TILES_PATH)
+    a = ap.parse_args()
+    doc = tune(a.ne, a.reps, out=a.out)
+    json.dump({k: v["epb"] for k, v in doc["tiles"].items()}, sys.stdout)
+    print()
+
+
+if __name__ == "__main__":
+    main()
