@@ -6,6 +6,7 @@ Every translation unit is compiled in parallel to an object under _build/,
 then linked into paper_2312_07725_amd/libnsfr.so.
 """
 import concurrent.futures
+import hashlib
 import os
 import shutil
 import subprocess
@@ -37,9 +38,9 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 
 
-def _compile(src):
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [hipcc(), *FLAGS, "-c", src, "-o", obj]
+def _compile(src, extra=(), tag=""):
+    obj = os.path.join(BUILD, os.path.basename(src) + tag + ".o")
+    cmd = [hipcc(), *FLAGS, *extra, "-c", src, "-o", obj]
     if src.endswith(".cpp"):
         cmd[1:1] = ["-x", "hip"]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -48,22 +49,25 @@ def _compile(src):
     return obj, r.stderr
 
 
-def build(verbose=False):
+def build(verbose=False, extra_flags=(), out=LIB):
+    """Compile and link; extra_flags (e.g. -D options) and out select a
+    variant build of the library."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = sources()
+    tag = "" if not extra_flags else "." + hashlib.sha1(" ".join(extra_flags).encode()).hexdigest()[:8]
     with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        results = list(ex.map(_compile, srcs))
+        results = list(ex.map(lambda f: _compile(f, tuple(extra_flags), tag), srcs))
     if verbose:
         for obj, err in results:
             if err.strip():
                 print(err, file=sys.stderr)
-    tmp = LIB + ".tmp"
+    tmp = out + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *[o for o, _ in results]]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

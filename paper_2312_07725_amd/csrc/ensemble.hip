@@ -85,7 +85,7 @@ static nsfr_status build_items(nsfr_ens* s) {
             int cnt = (int)std::min<int64_t>(epb, E - e0);
             items.push_back({f, (int)e0, cnt * n3 * per_node_pairs});
         }
-        lds = std::max(lds, (size_t)epb * 15 * n3 * sizeof(double));
+        lds = std::max(lds, (size_t)epb * stage_lds_doubles(n) * sizeof(double));
     }
     std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) { return a.cost > b.cost; });
     std::vector<int2> h(items.size());

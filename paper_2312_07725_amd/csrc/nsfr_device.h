@@ -55,6 +55,13 @@ __device__ __forceinline__ Prim primitives(double r, double m1, double m2, doubl
 // uses its series (same switch as the reference implementation).
 constexpr double LN_SWITCH = 1e-4;
 
+// Closed forms of the logarithmic mean and of its reciprocal, for the rare
+// pairs whose squared relative jump exceeds the series switch. Kept out of
+// line: inlined, the compiler hoists and shares the logarithms of the node
+// values across all pairs of a line and evaluates them unconditionally.
+__device__ __noinline__ double ln_mean_closed(double a, double b) { return (a - b) / (log(a) - log(b)); }
+__device__ __noinline__ double inv_ln_mean_closed(double a, double b) { return (log(a) - log(b)) / (a - b); }
+
 // Logarithmic mean (a - b) / (ln a - ln b). Series branch:
 // s / 2 * f / atanh(f) with f = (a - b) / s, u = f^2, and
 // f / atanh(f) = 1 - u/3 - 4u^2/45 - 44u^3/945 - ..., truncated after u^3
@@ -67,7 +74,7 @@ __device__ __forceinline__ double ln_mean(double a, double b) {
         double q = __builtin_fma(u, __builtin_fma(u, __builtin_fma(u, -44.0 / 945.0, -4.0 / 45.0), -1.0 / 3.0), 1.0);
         return 0.5 * s * q;
     }
-    return d / (log(a) - log(b));
+    return ln_mean_closed(a, b);
 }
 
 // Reciprocal of the logarithmic mean, (ln a - ln b) / (a - b); series branch
@@ -80,7 +87,7 @@ __device__ __forceinline__ double inv_ln_mean(double a, double b, double rs) {
         double q = __builtin_fma(u, __builtin_fma(u, __builtin_fma(u, 1.0 / 7.0, 1.0 / 5.0), 1.0 / 3.0), 1.0);
         return 2.0 * rs * q;
     }
-    return (log(a) - log(b)) / d;
+    return inv_ln_mean_closed(a, b);
 }
 
 // Entropy-conserving, kinetic-energy-preserving two-point flux f_s(A, B) . N

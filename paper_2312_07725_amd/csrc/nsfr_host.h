@@ -61,6 +61,7 @@ hipError_t launch_geometry(int p, const Ops& ops, int nx, int ny, int nz, double
                            double l, double* X, double* Cline, double* invWJ, double* J, hipStream_t s);
 hipError_t launch_stage(int p, bool cwa, int variant, const StageArgs& a, hipStream_t s);
 int default_epb(int p);
+int stage_lds_doubles(int n);
 int max_epb(int p);
 hipError_t launch_geometry_export(int p, int64_t E, const double* Cline, double* C, hipStream_t s);
 hipError_t launch_max_wavespeed(int64_t nnodes, const double* U, double gamma, double* partial, int nblk,

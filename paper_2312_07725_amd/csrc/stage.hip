@@ -42,39 +42,55 @@ __device__ __forceinline__ void line_geometry(int dir, int l, int& base, int& st
     else { base = t1 + N * t2; stride = N * N; }
 }
 
-// One pass of a rank-one line operator x <- x - vec (coef . x) along
-// direction dir for all (element, state, line) of the workgroup, in LDS.
+#ifndef NSFR_PAD
+#define NSFR_PAD 1
+#endif
+#ifndef NSFR_HALO_EARLY
+#define NSFR_HALO_EARLY 0
+#endif
+
+// LDS index of a node in the primitive block: one pad slot after every
+// xi-row when NSFR_PAD, so that the strided accesses of xi- and eta-lines
+// spread over the LDS banks.
 template <int N>
+__device__ __forceinline__ int pad_node(int node) {
+    return NSFR_PAD ? node + node / N : node;
+}
+
+// One pass of a rank-one line operator x <- x - vec (coef . x) along
+// direction dir for all (element, state, line) of the workgroup, in the LDS
+// accumulator [epb][5][PN3] (padded node index).
+template <int N, int PN3>
 __device__ __forceinline__ void line_pass(double* lr, int epb, int dir, const double* coef, const double* vec) {
-    constexpr int N2 = N * N, N3 = N2 * N;
+    constexpr int N2 = N * N;
     for (int it = threadIdx.x; it < epb * 5 * N2; it += blockDim.x) {
         int l = it % N2;
         int sl = it / N2;   // element * 5 + state
         int base, stride;
         line_geometry<N>(dir, l, base, stride);
-        double* x = lr + sl * N3 + base;
+        double* x = lr + sl * PN3;
         double v[N];
         double t = 0.0;
 #pragma unroll
         for (int a = 0; a < N; ++a) {
-            v[a] = x[a * stride];
+            v[a] = x[pad_node<N>(base + a * stride)];
             t += coef[a] * v[a];
         }
 #pragma unroll
-        for (int a = 0; a < N; ++a) x[a * stride] = v[a] - vec[a] * t;
+        for (int a = 0; a < N; ++a) x[pad_node<N>(base + a * stride)] = v[a] - vec[a] * t;
     }
 }
 
-// Primitive variables of a node from the LDS block [6][N3].
-template <int N3>
-__device__ __forceinline__ Prim lds_prim(const double* L, int node) {
+// Primitive variables of a node from the LDS block [6][PN3] (padded index).
+template <int PN3>
+__device__ __forceinline__ Prim lds_prim(const double* L, int pn) {
     Prim q;
-    q.rho = L[node];
-    q.u = L[N3 + node];
-    q.v = L[2 * N3 + node];
-    q.w = L[3 * N3 + node];
-    q.p = L[4 * N3 + node];
-    q.beta = L[5 * N3 + node];
+    q.rho = L[pn];
+    q.u = L[PN3 + pn];
+    q.v = L[2 * PN3 + pn];
+    q.w = L[3 * PN3 + pn];
+    q.p = L[4 * PN3 + pn];
+    q.beta = L[5 * PN3 + pn];
     return q;
 }
 
@@ -87,7 +103,9 @@ __device__ __forceinline__ Prim lds_prim(const double* L, int node) {
 // thread keeps only the residual of its line in registers.
 template <int P, bool CWA, int VARIANT>
 __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0, double* lds) {
-    constexpr int N = P + 1, N2 = N * N, N3 = N2 * N, LINES = 3 * N2, LDSE = 15 * N3;
+    constexpr int N = P + 1, N2 = N * N, N3 = N2 * N, LINES = 3 * N2;
+    constexpr int PN3 = NSFR_PAD ? N3 + N2 : N3;   // padded stride of a primitive component
+    constexpr int LDSE = 6 * PN3 + 9 * N3;          // LDS doubles per element
     const int tid = threadIdx.x, nth = blockDim.x;
     const int epb = A.epb;
     const int64_t E = A.geo.E;
@@ -102,16 +120,17 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
         if (e < E) {
             const double* U = A.Uin + e * N3 + node;
             Prim q = primitives(U[0], U[SE], U[2 * SE], U[3 * SE], U[4 * SE], gm1);
-            double* L = lds + el * LDSE + node;
+            double* L = lds + el * LDSE + pad_node<N>(node);
             L[0] = q.rho;
-            L[N3] = q.u;
-            L[2 * N3] = q.v;
-            L[3 * N3] = q.w;
-            L[4 * N3] = q.p;
-            L[5 * N3] = q.beta;
+            L[PN3] = q.u;
+            L[2 * PN3] = q.v;
+            L[3 * PN3] = q.w;
+            L[4 * PN3] = q.p;
+            L[5 * PN3] = q.beta;
             const double* Cg = A.geo.Cline + e * N3 + node;   // same offset in line-major order
+            double* Lc0 = lds + el * LDSE + 6 * PN3 + node;
 #pragma unroll
-            for (int k = 0; k < 9; ++k) L[(6 + k) * N3] = Cg[k * SE];
+            for (int k = 0; k < 9; ++k) Lc0[k * N3] = Cg[k * SE];
         }
     }
     __syncthreads();
@@ -126,8 +145,8 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
     const bool active = lt && (e < E);
     int base, stride;
     line_geometry<N>(dir, l, base, stride);
-    const double* Lp = lds + el * LDSE;                      // primitives
-    const double* Lc = lds + el * LDSE + (6 + 3 * dir) * N3 + l;   // metric column, [comp][pos][line]
+    const double* Lp = lds + el * LDSE;                             // primitives
+    const double* Lc = lds + el * LDSE + 6 * PN3 + 3 * dir * N3 + l;   // metric column, [comp][pos][line]
 
     // ---- 3. line residual: volume pairs, then the two endpoint face fluxes
     double R[5][N];
@@ -135,14 +154,37 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
     for (int s = 0; s < 5; ++s)
 #pragma unroll
         for (int a = 0; a < N; ++a) R[s][a] = 0.0;
+#if NSFR_HALO_EARLY
+    // neighbour data across the two ends of the line, requested before the
+    // pair sweep so that their latency overlaps it
+    double Um5[5], Up5[5], cmn[3], cpn[3];
+    if (active) {
+        const int64_t em = neighbour(e, dir, -1, A.geo.nx, A.geo.ny, A.geo.nz);
+        const int64_t ep = neighbour(e, dir, +1, A.geo.nx, A.geo.ny, A.geo.nz);
+        const double* Cm = A.geo.Cline + ((int64_t)(dir * 3) * E + em) * N3 + (N - 1) * N2 + l;
+        const double* Cp = A.geo.Cline + ((int64_t)(dir * 3) * E + ep) * N3 + l;
+        const double* Ubm = A.Uin + em * N3 + base + (N - 1) * stride;
+        const double* Ubp = A.Uin + ep * N3 + base;
+#pragma unroll
+        for (int s = 0; s < 5; ++s) {
+            Um5[s] = Ubm[s * SE];
+            Up5[s] = Ubp[s * SE];
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            cmn[k] = Cm[k * SE];
+            cpn[k] = Cp[k * SE];
+        }
+    }
+#endif
     if (active) {
 #pragma unroll
         for (int a = 0; a < N - 1; ++a) {
-            const Prim qa = lds_prim<N3>(Lp, base + a * stride);
+            const Prim qa = lds_prim<PN3>(Lp, pad_node<N>(base + a * stride));
             const double cax = Lc[a * N2], cay = Lc[N3 + a * N2], caz = Lc[2 * N3 + a * N2];
 #pragma unroll
             for (int b = a + 1; b < N; ++b) {
-                const Prim qb = lds_prim<N3>(Lp, base + b * stride);
+                const Prim qb = lds_prim<PN3>(Lp, pad_node<N>(base + b * stride));
                 const double cbx = Lc[b * N2], cby = Lc[N3 + b * N2], cbz = Lc[2 * N3 + b * N2];
                 double F[5];
                 // direction C(a) + C(b) = 2 N; the 1/2 is folded into S1h
@@ -159,8 +201,9 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
 #pragma unroll
         for (int side = 0; side < 2; ++side) {
             const int aown = side ? N - 1 : 0;
-            const int anbr = side ? 0 : N - 1;
             const double sg = side ? 0.5 : -0.5;   // outward reference normal / 2
+#if !NSFR_HALO_EARLY
+            const int anbr = side ? 0 : N - 1;
             const int64_t en = neighbour(e, dir, side ? 1 : -1, A.geo.nx, A.geo.ny, A.geo.nz);
             const double* Cn = A.geo.Cline + ((int64_t)(dir * 3) * E + en) * N3 + anbr * N2 + l;
             const double* Ub = A.Uin + en * N3 + base + anbr * stride;
@@ -168,8 +211,14 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
 #pragma unroll
             for (int s = 0; s < 5; ++s) Un5[s] = Ub[s * SE];
             const double cnx = Cn[0], cny = Cn[SE], cnz = Cn[2 * SE];
+#else
+            double Un5[5];
+#pragma unroll
+            for (int s = 0; s < 5; ++s) Un5[s] = side ? Up5[s] : Um5[s];
+            const double cnx = side ? cpn[0] : cmn[0], cny = side ? cpn[1] : cmn[1], cnz = side ? cpn[2] : cmn[2];
+#endif
             const Prim qn = primitives(Un5[0], Un5[1], Un5[2], Un5[3], Un5[4], gm1);
-            const Prim qo = lds_prim<N3>(Lp, base + aown * stride);
+            const Prim qo = lds_prim<PN3>(Lp, pad_node<N>(base + aown * stride));
             const double nx = sg * (Lc[aown * N2] + cnx), ny = sg * (Lc[N3 + aown * N2] + cny),
                          nz = sg * (Lc[2 * N3 + aown * N2] + cnz);
             double F[5];
@@ -185,6 +234,31 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
             for (int s = 0; s < 5; ++s) R[s][aown] += F[s];
         }
     }
+    // The node-parallel epilogue gives thread tid the nodes tid + j * nth,
+    // j < KP (nth >= epb * 3 N^2). Request their global operands now, so that
+    // the latency overlaps the LDS reduction and the mass-inverse passes.
+    constexpr int KP = (N + 2) / 3;
+    const int mode = A.mode;
+    double pf_iw[KP], pf_a[KP][5], pf_b[KP][5];
+#pragma unroll
+    for (int j = 0; j < KP; ++j) {
+        const int idx = tid + j * nth;
+        const int eli = idx / N3, node = idx - eli * N3;
+        const int64_t ee = e0 + eli;
+        pf_iw[j] = 0.0;
+#pragma unroll
+        for (int s = 0; s < 5; ++s) pf_a[j][s] = pf_b[j][s] = 0.0;
+        if (idx < epb * N3 && ee < E && mode != MODE_RESIDUAL) {
+            const int64_t g = ee * N3 + node;
+            pf_iw[j] = A.geo.invWJ[g];
+            const double* pa = mode == MODE_RK1 ? A.Uin : A.acc;
+#pragma unroll
+            for (int s = 0; s < 5; ++s) {
+                if (mode >= MODE_RK1) pf_a[j][s] = pa[s * SE + g];
+                if (mode == MODE_RK2 || mode == MODE_RK3) pf_b[j][s] = A.Un[s * SE + g];
+            }
+        }
+    }
     __syncthreads();   // all LDS line reads are done; the primitive block becomes the accumulator
 
     // ---- 4. sum the three directions in LDS ([epb][5][N3] at the element's
@@ -193,21 +267,21 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
     const double wperp = A.ops.w[l % N] * A.ops.w[l / N];
     for (int ph = 0; ph < 3; ++ph) {
         if (active && dir == ph) {
-            double* x = lr + el * 5 * N3 + base;
+            double* x = lr + el * 5 * PN3;
 #pragma unroll
             for (int s = 0; s < 5; ++s)
 #pragma unroll
                 for (int a = 0; a < N; ++a) {
-                    double v = R[s][a] * wperp;
-                    if (ph == 0) x[s * N3 + a * stride] = v;
-                    else x[s * N3 + a * stride] += v;
+                    const double v = R[s][a] * wperp;
+                    const int pn = s * PN3 + pad_node<N>(base + a * stride);
+                    if (ph == 0) x[pn] = v;
+                    else x[pn] += v;
                 }
         }
         __syncthreads();
     }
 
     // ---- 5. source, mass inverse, RK combination (node-parallel)
-    const int mode = A.mode;
     double dt = 0.0, cstage = 0.0;
     if (mode >= MODE_RK1) {
         dt = *A.dt;
@@ -223,9 +297,9 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
                 const double* X = A.geo.X + ee * N3 + node;
                 mms_source(X[0], X[SE], X[2 * SE], t, A.gamma, qs);
                 double wj = 1.0 / A.geo.invWJ[ee * N3 + node];
-                double* x = lr + eli * 5 * N3 + node;
+                double* x = lr + eli * 5 * PN3 + pad_node<N>(node);
 #pragma unroll
-                for (int s = 0; s < 5; ++s) x[s * N3] -= wj * qs[s];
+                for (int s = 0; s < 5; ++s) x[s * PN3] -= wj * qs[s];
             }
         }
         __syncthreads();
@@ -236,55 +310,60 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
             int64_t ee = e0 + eli;
             if (ee < E) {
 #pragma unroll
-                for (int s = 0; s < 5; ++s) A.out[s * SE + ee * N3 + node] = lr[(eli * 5 + s) * N3 + node];
+                for (int s = 0; s < 5; ++s)
+                    A.out[s * SE + ee * N3 + node] = lr[(eli * 5 + s) * PN3 + pad_node<N>(node)];
             }
         }
         return;
     }
     if (CWA) {
         for (int d = 0; d < 3; ++d) {   // Pi~^T along xi, eta, zeta
-            line_pass<N>(lr, epb, d, A.ops.pia, A.ops.pib);
+            line_pass<N, PN3>(lr, epb, d, A.ops.pia, A.ops.pib);
             __syncthreads();
         }
-        for (int idx = tid; idx < epb * N3; idx += nth) {
-            int eli = idx / N3, node = idx - eli * N3;
-            int64_t ee = e0 + eli;
-            double iw = (ee < E) ? A.geo.invWJ[ee * N3 + node] : 0.0;
 #pragma unroll
-            for (int s = 0; s < 5; ++s) lr[(eli * 5 + s) * N3 + node] *= iw;
+        for (int j = 0; j < KP; ++j) {
+            const int idx = tid + j * nth;
+            if (idx < epb * N3) {
+                const int eli = idx / N3, node = idx - eli * N3;
+#pragma unroll
+                for (int s = 0; s < 5; ++s) lr[(eli * 5 + s) * PN3 + pad_node<N>(node)] *= pf_iw[j];
+            }
         }
         __syncthreads();
         for (int d = 0; d < 3; ++d) {   // Pi~ along xi, eta, zeta
-            line_pass<N>(lr, epb, d, A.ops.pib, A.ops.pia);
+            line_pass<N, PN3>(lr, epb, d, A.ops.pib, A.ops.pia);
             __syncthreads();
         }
     }
-    for (int idx = tid; idx < epb * N3; idx += nth) {
-        int eli = idx / N3, node = idx - eli * N3;
-        int64_t ee = e0 + eli;
-        if (ee >= E) continue;
+#pragma unroll
+    for (int j = 0; j < KP; ++j) {
+        const int idx = tid + j * nth;
+        const int eli = idx / N3, node = idx - eli * N3;
+        const int64_t ee = e0 + eli;
+        if (idx >= epb * N3 || ee >= E) continue;
         const int64_t g = ee * N3 + node;
-        const double iw = CWA ? 1.0 : A.geo.invWJ[g];
+        const double iw = CWA ? 1.0 : pf_iw[j];
 #pragma unroll
         for (int s = 0; s < 5; ++s) {
-            const double k = -(lr[(eli * 5 + s) * N3 + node] * iw);
+            const double k = -(lr[(eli * 5 + s) * PN3 + pad_node<N>(node)] * iw);
             const int64_t gi = s * SE + g;
             switch (mode) {
                 case MODE_RHS: A.out[gi] = k; break;
                 case MODE_RK1: {
-                    double u = A.Uin[gi];
+                    const double u = pf_a[j][s];
                     A.acc[gi] = __builtin_fma(dt / 6.0, k, u);
                     A.out[gi] = __builtin_fma(0.5 * dt, k, u);
                 } break;
                 case MODE_RK2: {
-                    A.acc[gi] = __builtin_fma(dt / 3.0, k, A.acc[gi]);
-                    A.out[gi] = __builtin_fma(0.5 * dt, k, A.Un[gi]);
+                    A.acc[gi] = __builtin_fma(dt / 3.0, k, pf_a[j][s]);
+                    A.out[gi] = __builtin_fma(0.5 * dt, k, pf_b[j][s]);
                 } break;
                 case MODE_RK3: {
-                    A.acc[gi] = __builtin_fma(dt / 3.0, k, A.acc[gi]);
-                    A.out[gi] = __builtin_fma(dt, k, A.Un[gi]);
+                    A.acc[gi] = __builtin_fma(dt / 3.0, k, pf_a[j][s]);
+                    A.out[gi] = __builtin_fma(dt, k, pf_b[j][s]);
                 } break;
-                default: A.out[gi] = __builtin_fma(dt / 6.0, k, A.acc[gi]); break;
+                default: A.out[gi] = __builtin_fma(dt / 6.0, k, pf_a[j][s]); break;
             }
         }
     }
@@ -340,13 +419,13 @@ hipError_t launch_ensemble_stage(const StageArgs* table, const int2* items, int 
     return hipGetLastError();
 }
 
-// LDS per element of the stage kernel (doubles): primitives + metric columns
-constexpr int stage_lds_doubles(int n3) { return 15 * n3; }
+// LDS per element of the stage kernel (doubles): primitives (padded) + metric columns
+int stage_lds_doubles(int n) { return 6 * (n * n * n + (NSFR_PAD ? n * n : 0)) + 9 * n * n * n; }
 
 int max_epb(int p) {
-    const int n = p + 1, lines = 3 * n * n, n3 = n * n * n;
+    const int n = p + 1, lines = 3 * n * n;
     const int by_threads = STAGE_BLOCK_MAX / lines;
-    const int by_lds = (int)(65536 / (stage_lds_doubles(n3) * sizeof(double)));
+    const int by_lds = (int)(65536 / (stage_lds_doubles(n) * sizeof(double)));
     return by_threads < by_lds ? by_threads : by_lds;
 }
 
@@ -363,7 +442,7 @@ template <int P, bool CWA, int V>
 static hipError_t launch_t(const StageArgs& a, hipStream_t s) {
     constexpr int N = P + 1, N3 = N * N * N, LINES = 3 * N * N;
     int threads = ((a.epb * LINES + 63) / 64) * 64;
-    size_t lds = (size_t)a.epb * stage_lds_doubles(N3) * sizeof(double);
+    size_t lds = (size_t)a.epb * stage_lds_doubles(N) * sizeof(double);
     unsigned blocks = (unsigned)((a.geo.E + a.epb - 1) / a.epb);
     stage_kernel<P, CWA, V><<<blocks, threads, lds, s>>>(a);
     return hipGetLastError();

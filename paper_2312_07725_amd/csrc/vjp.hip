@@ -19,6 +19,26 @@ namespace nsfr {
 
 constexpr int VJP_BLOCK_MAX = 512;
 
+// Closed-form branches of the two derivative helpers below, kept out of line
+// so that their logarithms are only evaluated for the rare pairs that need them.
+__device__ __noinline__ void ln_mean_grad_closed(double a, double b, double& La, double& Lb, double& L) {
+    double la = log(a), lb = log(b);
+    double il = 1.0 / (la - lb);
+    L = (a - b) * il;
+    La = (1.0 - L / a) * il;
+    Lb = (L / b - 1.0) * il;
+}
+
+__device__ __noinline__ void inv_ln_mean_grad_closed(double a, double b, double& Ia, double& Ib, double& I) {
+    double la = log(a), lb = log(b);
+    double L = (a - b) / (la - lb);
+    I = 1.0 / L;
+    double il = 1.0 / (la - lb);
+    double La = (1.0 - L / a) * il, Lb = (L / b - 1.0) * il;
+    Ia = -I * I * La;
+    Ib = -I * I * Lb;
+}
+
 // d/da and d/db of the logarithmic mean L(a, b) (homogeneous of degree one):
 // with s = a + b, f = (a - b)/s and G(f) = f / atanh(f),
 // dL/da = (G + G' (1 - f)) / 2, dL/db = (G - G' (1 + f)) / 2.
@@ -34,11 +54,7 @@ __device__ __forceinline__ void ln_mean_grad(double a, double b, double& La, dou
         La = 0.5 * (G + Gp * (1.0 - f));
         Lb = 0.5 * (G - Gp * (1.0 + f));
     } else {
-        double la = log(a), lb = log(b);
-        double il = 1.0 / (la - lb);
-        L = d * il;
-        La = (1.0 - L / a) * il;
-        Lb = (L / b - 1.0) * il;
+        ln_mean_grad_closed(a, b, La, Lb, L);
     }
 }
 
@@ -56,13 +72,7 @@ __device__ __forceinline__ void inv_ln_mean_grad(double a, double b, double rs, 
         Ia = k * (-H + Hp * (1.0 - f));
         Ib = k * (-H - Hp * (1.0 + f));
     } else {
-        double la = log(a), lb = log(b);
-        double L = d / (la - lb);
-        I = 1.0 / L;
-        double il = 1.0 / (la - lb);
-        double La = (1.0 - L / a) * il, Lb = (L / b - 1.0) * il;
-        Ia = -I * I * La;
-        Ib = -I * I * Lb;
+        inv_ln_mean_grad_closed(a, b, Ia, Ib, I);
     }
 }
 

@@ -13,7 +13,9 @@ from ctypes import POINTER, byref, c_double, c_int32, c_int64, c_void_p, c_char_
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libnsfr.so")
+# NSFR_LIB selects another build of the library (e.g. a variant compiled with
+# different kernel options); by default the in-tree build is used.
+LIB_PATH = os.environ.get("NSFR_LIB") or os.path.join(_HERE, "libnsfr.so")
 
 NSFR_OK, NSFR_EINVAL, NSFR_ENOMEM, NSFR_EHIP, NSFR_EUNPHYSICAL, NSFR_ENOTSUP = 0, -1, -2, -3, -4, -5
 
