@@ -159,4 +159,67 @@ __device__ __forceinline__ void mms_source(double x, double y, double z, double 
     q[4] = c4 * cs + c5 * s2;
 }
 
+
+// ---- indexing helpers shared by the element kernels
+
+// Periodic neighbour of element e across the face (dir, side = +-1).
+__device__ __forceinline__ int64_t neighbour(int64_t e, int dir, int side, int nx, int ny, int nz) {
+    int ex = (int)(e % nx);
+    int64_t r = e / nx;
+    int ey = (int)(r % ny);
+    int ez = (int)(r / ny);
+    if (dir == 0) ex = (ex + side + nx) % nx;
+    else if (dir == 1) ey = (ey + side + ny) % ny;
+    else ez = (ez + side + nz) % nz;
+    return ex + (int64_t)nx * (ey + (int64_t)ny * ez);
+}
+
+// Node index of position 0 and the node stride along line l of direction dir
+// (line index l = t1 + N t2 over the two tangential indices).
+template <int N>
+__device__ __forceinline__ void line_geometry(int dir, int l, int& base, int& stride) {
+    const int t1 = l % N, t2 = l / N;
+    if (dir == 0) { base = N * t1 + N * N * t2; stride = 1; }
+    else if (dir == 1) { base = t1 + N * N * t2; stride = N; }
+    else { base = t1 + N * t2; stride = N * N; }
+}
+
+#ifndef NSFR_PAD
+#define NSFR_PAD 1
+#endif
+#ifndef NSFR_HALO_EARLY
+#define NSFR_HALO_EARLY 0
+#endif
+
+// LDS index of a node in the primitive block: one pad slot after every
+// xi-row when NSFR_PAD, so that the strided accesses of xi- and eta-lines
+// spread over the LDS banks.
+template <int N>
+__device__ __forceinline__ int pad_node(int node) {
+    return NSFR_PAD ? node + node / N : node;
+}
+
+// Primitive variables of a node from the LDS block [6][PN3] (padded index).
+template <int PN3>
+__device__ __forceinline__ Prim lds_prim(const double* L, int pn) {
+    Prim q;
+    q.rho = L[pn];
+    q.u = L[PN3 + pn];
+    q.v = L[2 * PN3 + pn];
+    q.w = L[3 * PN3 + pn];
+    q.p = L[4 * PN3 + pn];
+    q.beta = L[5 * PN3 + pn];
+    return q;
+}
+
+// Workgroups are dispatched to the 8 XCDs round-robin; remap the workgroup
+// index so that each XCD processes one contiguous range of elements, which
+// keeps most face-neighbour reads inside that XCD's L2.
+__device__ __forceinline__ int xcd_remap(int g, int nb) {
+    constexpr int NX = 8;
+    const int q = nb / NX, r = nb % NX;
+    const int x = g % NX, k = g / NX;
+    return (x < r) ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
 }  // namespace nsfr
