@@ -51,7 +51,7 @@ typedef enum {
     NSFR_ENOMEM = -2,        /* device allocation failed                      */
     NSFR_EHIP = -3,          /* a HIP runtime call or kernel launch failed    */
     NSFR_EUNPHYSICAL = -4,   /* non-positive density or pressure, or NaN      */
-    NSFR_ENOTSUP = -5        /* valid request this build does not implement   */
+    NSFR_ENOTSUP = -5        /* valid request the library does not implement  */
 } nsfr_status;
 
 typedef struct {

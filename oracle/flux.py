@@ -137,9 +137,11 @@ def ec_flux(Ua, Ub, N, gamma, variant=0):
 def llf_dissipation(Ua, Ub, N, gamma):
     """Local Lax-Friedrichs term -|N| lambda_max (Ub - Ua) / 2 added to the EC
     surface flux for the manufactured-solution runs (the paper adds an upwind
-    dissipation there; this build's reading uses LLF on conservative jumps).
+    dissipation there, read here as LLF on the conservative jumps).
     lambda_max = max over both sides of |u . N/|N|| + sqrt(gamma p / rho).
-    Real tensors only. Parity unpinned beyond antisymmetry and zero jump."""
+    Real tensors only. Pinned by a hand-computed pair, antisymmetry, zero jump
+    and entropy dissipation (the jump of the entropy variables times this term
+    is never positive)."""
     ra, va, pa, _ = primitives(Ua, gamma)
     rb, vb, pb, _ = primitives(Ub, gamma)
     nn = torch.sqrt(N[0] ** 2 + N[1] ** 2 + N[2] ** 2)

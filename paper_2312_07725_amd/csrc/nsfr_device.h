@@ -190,6 +190,9 @@ __device__ __forceinline__ void line_geometry(int dir, int l, int& base, int& st
 #ifndef NSFR_HALO_EARLY
 #define NSFR_HALO_EARLY 0
 #endif
+#ifndef NSFR_PREFETCH
+#define NSFR_PREFETCH 1
+#endif
 
 // LDS index of a node in the primitive block: one pad slot after every
 // xi-row when NSFR_PAD, so that the strided accesses of xi- and eta-lines

@@ -134,3 +134,28 @@ def test_llf_dissipation_properties():
     d2 = fx.llf_dissipation(Ub, Ua, [-x for x in N], G)
     assert torch.allclose(d1, -d2, rtol=0, atol=0)
     assert float(fx.llf_dissipation(Ua, Ua, N, G).abs().max()) == 0.0
+
+
+def test_llf_dissipation_hand_computed_pair():
+    # Ua: rho 1, u (0.5, 0, 0), p 1; Ub: rho 1.2, at rest, p 0.8; N = (2, 0, 0).
+    # Wave speeds: 0.5 + sqrt(1.4) on the left, sqrt(1.4 * 0.8 / 1.2) on the
+    # right; the left one is larger. Conservative jump Ub - Ua:
+    # (0.2, -0.5, 0, 0, 2.0 - 2.625).
+    one = lambda v: torch.tensor([v], dtype=torch.float64)  # noqa: E731
+    Ua = fx.conservative(one(1.0), [one(0.5), one(0.0), one(0.0)], one(1.0), G)
+    Ub = fx.conservative(one(1.2), [one(0.0), one(0.0), one(0.0)], one(0.8), G)
+    N = [one(2.0), one(0.0), one(0.0)]
+    lam = 0.5 + math.sqrt(1.4)
+    jump = [0.2, -0.5, 0.0, 0.0, -0.625]
+    d = fx.llf_dissipation(Ua, Ub, N, G)[:, 0]
+    for s in range(5):
+        assert abs(float(d[s]) - (-0.5 * 2.0 * lam * jump[s])) < 1e-14
+
+
+def test_llf_dissipation_is_entropy_dissipative():
+    Ua, Ub = rand_states(500, 16), rand_states(500, 17)
+    g = torch.Generator().manual_seed(18)
+    N = [torch.randn(500, generator=g, dtype=torch.float64) for _ in range(3)]
+    d = fx.llf_dissipation(Ua, Ub, N, G)
+    dv = fx.entropy_variables(Ub, G) - fx.entropy_variables(Ua, G)
+    assert float((dv * d).sum(0).max()) <= 0.0
