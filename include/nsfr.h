@@ -6,7 +6,8 @@
  *
  * Discretisation (all FP64):
  *   - solution, volume and surface quadrature on the p+1 Legendre-Gauss-Lobatto
- *     (LGL) nodes per direction, nodal Lagrange basis (Sec. 2.2, Sec. 6);
+ *     (LGL) nodes per direction, nodal Lagrange basis (Sec. 2.2; Sec. 7 opening
+ *     paragraph);
  *   - volume term: entropy-conserving two-point flux differencing, the
  *     Hadamard product of the hybridised skew-symmetric operator with the
  *     metric-split reference two-point flux (Eq. NSFR), evaluated line by
@@ -16,7 +17,8 @@
  *     FR-modified mass (Eq. NSFR, last term; Sec. 3.2);
  *   - mass: weight-adjusted inverse Pi~ (W J)^-1 Pi~^T of the FR-modified mass
  *     (Eq. weight-adj ESFR mass, Eq. Fr projection);
- *   - time: classical four-stage RK4 (Sec. 6).
+ *   - time: four-stage fourth-order RK, read as classical RK4 (Sec. 7, opening
+ *     paragraph).
  *
  * Data layout. Every state-sized array is contiguous FP64 device memory of
  * 5 * E * (p+1)^3 doubles in the order [state][element][k][j][i], i (xi)
@@ -66,7 +68,7 @@ typedef struct {
                              mean pressure); 1: plain Chandrashekar flux                 */
     int32_t surface_diss; /* 0: entropy-conserving surface flux; 1: plus local
                              Lax-Friedrichs dissipation                                  */
-    int32_t source;       /* 0: none; 1: manufactured-solution source of Sec. 6.1        */
+    int32_t source;       /* 0: none; 1: manufactured-solution source of Sec. 7.1        */
     int32_t tile;         /* elements per workgroup of the stage kernel; 0 = default     */
 } nsfr_config;
 
@@ -117,10 +119,13 @@ nsfr_status nsfr_rk4_step(nsfr_ctx* ctx, double* U, const double* dt_dev, double
 nsfr_status nsfr_rk4_run(nsfr_ctx* ctx, double* U, const double* dt_dev, double* t_dev,
                          int32_t nsteps, double* work);
 
-/* lam_dev[0] = max over nodes of |u| + sqrt(gamma p / rho). */
+/* lam_dev[0] = max over nodes of |u| + sqrt(gamma p / rho): the maximum wave
+ * speed on which Sec. 7 (opening paragraph) bases its adaptive time step.
+ * U is a state-sized device array; lam_dev is one device double. */
 nsfr_status nsfr_max_wavespeed(nsfr_ctx* ctx, const double* U, double* lam_dev);
 
-/* dt_dev[0] = cfl * (hi - lo) / (ne[0] (p+1)) / (max wave speed) (Sec. 6). */
+/* dt_dev[0] = cfl * (hi - lo) / (ne[0] (p+1)) / (max wave speed): the adaptive
+ * step of Sec. 7 (opening paragraph), CFL = cfl, dx the mean node spacing. */
 nsfr_status nsfr_cfl_dt(nsfr_ctx* ctx, const double* U, double cfl, double* dt_dev);
 
 /* Vector-Jacobian product g = (d(dU/dt)/dU)^T lam of nsfr_rhs at (U, t),
@@ -135,7 +140,7 @@ nsfr_status nsfr_rhs_vjp(nsfr_ctx* ctx, const double* U, const double* lam, doub
 nsfr_status nsfr_rk4_step_vjp(nsfr_ctx* ctx, const double* U, const double* dt_dev, double t,
                               const double* lam_next, double* lam, double* work);
 
-/* Diagnostics of R(U, t) (Sec. 5.2, 5.3, 6.3) into device array out (8 doubles):
+/* Diagnostics of R(U, t) (Sec. 6.2, 6.3, 7.3) into device array out (8 doubles):
  * [sum v.R, sum |v.R|, sum R_rho, sum R_mx, sum R_my, sum R_mz, sum R_E, max |R|],
  * v the entropy variables. Uses the library workspace. */
 nsfr_status nsfr_diagnostics(nsfr_ctx* ctx, const double* U, double t, double* out);
@@ -173,7 +178,7 @@ nsfr_status nsfr_ens_set_tile(nsfr_ens* ens, int32_t p, int32_t epb);
 
 /* FR parameter c_HU (convention of Eq. Km) for degree p (2..5): the value for
  * which the FR-modified 1D mass of the exactly integrated Lagrange basis on
- * LGL nodes equals the collocated LGL mass (Sec. 6.2). c_HU = E_p / (2 (p!)^2)
+ * LGL nodes equals the collocated LGL mass (Sec. 7.2). c_HU = E_p / (2 (p!)^2)
  * with E_p the LGL quadrature error of x^(2p). Host output. */
 nsfr_status nsfr_c_hu(int32_t p, double* c_out);
 

@@ -4,7 +4,7 @@
 Paper: Sec. 2.1 (entropy variables v = U'(u), entropy potential, Tadmor's
 shuffle condition, Eq. EC flux; 3D Euler system and its fluxes), Sec. 3.3
 (two-point flux choice: Chandrashekar's flux in the variables rho, u and
-beta = rho / (2p)) and Sec. 6 (the experiments use Chandrashekar's flux with
+beta = rho / (2p)) and Sec. 7 opening paragraph (the experiments use Chandrashekar's flux with
 Ranocha's pressure fix in volume and surface).
 
 Readings of the paper used here:
@@ -152,7 +152,7 @@ def llf_dissipation(Ua, Ub, N, gamma):
 
 
 def max_wavespeed(U, gamma):
-    """max over nodes of |u| + sqrt(gamma p / rho) (Sec. 6: adaptive step)."""
+    """max over nodes of |u| + sqrt(gamma p / rho) (Sec. 7 opening paragraph: adaptive step)."""
     rho, vel, p, _ = primitives(U, gamma)
     speed = torch.sqrt(vel[0] ** 2 + vel[1] ** 2 + vel[2] ** 2) + torch.sqrt(gamma * p / rho)
     return float(speed.max())

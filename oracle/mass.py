@@ -30,19 +30,6 @@ def wa_apply(mesh, c, R):
     return z.reshape_as(R)
 
 
-def wa_apply_abs(mesh, c, R):
-    """|Pi3| diag(1/(W J)) |Pi3|^T R with elementwise absolute values of the
-    projection: the magnitude bound of A R used as the round-off scale of
-    parity checks (not part of the scheme)."""
-    ops = Operators1D(mesh.p, c)
-    P3 = kron3(ops.Pi, ops.Pi, ops.Pi).abs().to(R.dtype)
-    S, E = R.shape[0], R.shape[1]
-    Nv = mesh.n ** 3
-    y = torch.einsum("ji,sej->sei", P3, R.reshape(S, E, Nv))
-    y = y * mesh.invWJ.reshape(E, Nv)
-    return torch.einsum("ij,sej->sei", P3, y).reshape_as(R)
-
-
 def modified_mass(mesh, c):
     """Dense M_m + K_m for every element, shape (E, Nv, Nv) (Eq. Km with the
     collocated LGL basis, so M_m = diag(W J))."""

@@ -1,7 +1,7 @@
 """Warped periodic hexahedral mesh and metric terms (oracle; test infrastructure).
 
 Paper: Sec. 2.2 (mapping, covariant/contravariant bases, Jacobian J, metric
-cofactor matrix C with C^T = J (J^Omega)^-1, discrete GCL, Eq. GCL) and Sec. 6
+cofactor matrix C with C^T = J (J^Omega)^-1, discrete GCL, Eq. GCL) and Sec. 7
 (nonsymmetric warped map, Eq. warped grid).
 
 Layout: a nodal field on the mesh is a tensor of shape (E, n, n, n) indexed

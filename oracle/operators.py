@@ -3,7 +3,7 @@ infrastructure only).
 
 Paper: Sec. 2.2 (tensor-product basis, SBP property Eq. SBP), Sec. 3.2 (ESFR
 correction operator, Eq. Km), Sec. 4 (ESFR projection, Eq. Fr projection) and
-Sec. 6.3 (c_HU makes the modified mass equal to the LGL collocated mass).
+Sec. 7.2 (c_HU makes the modified mass equal to the LGL collocated mass).
 
 The solution is a nodal Lagrange basis collocated on the p+1 LGL nodes, so the
 basis evaluated at the volume quadrature nodes is the identity and the 1D mass
@@ -111,7 +111,7 @@ class Operators1D:
 
 def c_hu(p):
     """FR parameter c_HU (Eq. Km convention) for which the modified 1D mass on
-    LGL nodes equals the exactly integrated Lagrange mass (Sec. 6.3).
+    LGL nodes equals the exactly integrated Lagrange mass (Sec. 7.2).
 
     Derived from the requirement M_exact + c (D^p)^T W D^p = W_LGL, where
     M_exact is the exactly integrated mass of the LGL Lagrange basis, computed

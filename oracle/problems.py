@@ -1,9 +1,9 @@
-"""Manufactured solution of Sec. 6.1 (oracle; test infrastructure only).
+"""Manufactured solution of Sec. 7.1 (oracle; test infrastructure only).
 
-Paper: Sec. 6.1 -- density 2 + sin(pi (x + y + z - 2t)) / 10, unit velocity in
+Paper: Sec. 7.1 -- density 2 + sin(pi (x + y + z - 2t)) / 10, unit velocity in
 every direction, rho e = rho^2, and the printed unsteady source q with
 constants c1..c5 (c3 read as (pi/100)(gamma - 1): the printed comma is a
-typesetting slip). Also the L2 error of Sec. 6.1 with the W J weights.
+typesetting slip). Also the L2 error of Sec. 7.1 with the W J weights.
 """
 import math
 
@@ -18,7 +18,7 @@ def mms_state(X, t, gamma):
 
 
 def mms_source(X, t, gamma):
-    """Source q(x, t) of Sec. 6.1, shape (5, ...)."""
+    """Source q(x, t) of Sec. 7.1, shape (5, ...)."""
     pi = math.pi
     c1 = pi / 10.0
     c2 = -pi / 5.0 + pi / 20.0 * (1.0 + 5.0 * gamma)
@@ -32,6 +32,6 @@ def mms_source(X, t, gamma):
 
 
 def l2_error(mesh, U, Uex):
-    """sqrt(sum_m (u_m - u_ex)^T W J_m (u_m - u_ex)) per state (Sec. 6.1)."""
+    """sqrt(sum_m (u_m - u_ex)^T W J_m (u_m - u_ex)) per state (Sec. 7.1)."""
     d = U - Uex
     return torch.sqrt((d * d * mesh.WJ).reshape(U.shape[0], -1).sum(1))

@@ -100,47 +100,6 @@ def residual(mesh, U, gamma, variant=0, dissipation=False, two_point=None):
     return volume_residual(mesh, U, gamma, tp) + surface_residual(mesh, U, gamma, tp, diss)
 
 
-def residual_magnitude(mesh, U, gamma, variant=0, dissipation=False):
-    """Per node and state, the sum of the magnitudes of every term the residual
-    adds there: sum_k sum_a' |S1[a, a']| w_perp |f_s| + W_f |f*|.
-
-    Not part of the scheme: it bounds the round-off of any evaluation of R
-    (each term rounded a few times), so it is the scale against which two
-    evaluations with different operation orders are compared. Where the terms
-    cancel (smooth, nearly steady states such as the Taylor-Green vortex, whose
-    density residual is pure truncation error) max |R| is far smaller than this
-    scale and unusable as a reference."""
-    tp = ec_two_point(gamma, variant)
-    S1a, w = mesh.ops.S1.abs(), mesh.ops.w
-    wperp = (w[:, None] * w[None, :])[:, :, None]
-    M = torch.zeros_like(U)
-    for k in range(3):
-        Uk = _line_last(U, k)
-        Ck = _line_last(mesh.C[:, k], k)
-        N = [0.5 * (Ck[i][..., :, None] + Ck[i][..., None, :]) for i in range(3)]
-        F = tp(Uk[..., :, None], Uk[..., None, :], N).abs()
-        M = M + _line_back(torch.einsum("ij,...ij->...i", S1a, F) * wperp, k)
-    diss = (lambda a, b, N: fx.llf_dissipation(a, b, N, gamma)) if dissipation else None
-    Wf = w[:, None] * w[None, :]
-    n = mesh.n
-    for k in range(3):
-        Mk = torch.zeros_like(_line_last(U, k))
-        for side in (-1, 1):
-            fs = face_flux(mesh, U, k, side, gamma, tp, None).abs()
-            if diss is not None:
-                Un = mesh.neighbor(U, k, side)
-                ao, an = (n - 1, 0) if side > 0 else (0, n - 1)
-                Cn = mesh.neighbor(mesh.C[:, k], k, side)
-                Co = _line_last(mesh.C[:, k], k)[..., ao]
-                Cb = _line_last(Cn, k)[..., an]
-                Nf = [side * 0.5 * (Co[i] + Cb[i]) for i in range(3)]
-                fs = fs + diss(_line_last(U, k)[..., ao], _line_last(Un, k)[..., an], Nf).abs()
-            idx = n - 1 if side > 0 else 0
-            Mk[..., idx] = Mk[..., idx] + Wf * fs
-        M = M + _line_back(Mk, k)
-    return M
-
-
 # ---------------------------------------------------------------------------
 # Definition form: the dense hybridised operator of Eq. skew-symm qtilde oper
 # ---------------------------------------------------------------------------

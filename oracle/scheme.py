@@ -2,7 +2,7 @@
 
 Paper: Eq. NSFR with the weight-adjusted inverse of Eq. weight-adj ESFR mass:
     du/dt = -A (R_vol + R_surf - W J q),  A ~= (M_m + K_m)^-1,
-where q is the manufactured source of Sec. 6.1 when enabled (reading: the
+where q is the manufactured source of Sec. 7.1 when enabled (reading: the
 source enters like the DG source term chi^T W J q and is then multiplied by the
 inverse modified mass, as every right-hand-side term is).
 """
@@ -12,9 +12,9 @@ import torch
 
 from . import flux as fx
 from .mesh import Mesh
-from .mass import wa_apply, wa_apply_abs, exact_apply
+from .mass import wa_apply, exact_apply
 from .problems import mms_source
-from .residual import residual, residual_definition, residual_magnitude
+from .residual import residual, residual_definition
 from .timestep import rk4_step, cfl_dt
 
 
@@ -46,17 +46,6 @@ class Scheme:
     def rhs(self, U, t=0.0, definition=False):
         """du/dt = -A R."""
         return -self.apply_inverse_mass(self.residual(U, t, definition))
-
-    def residual_scale(self, U, t=0.0):
-        """Round-off scale of R: sum of the magnitudes of its terms per node."""
-        M = residual_magnitude(self.mesh, U, self.gamma, self.variant, self.dissipation)
-        if self.source:
-            M = M + (self.mesh.WJ * mms_source(self.mesh.X, t, self.gamma)).abs()
-        return M
-
-    def rhs_scale(self, U, t=0.0):
-        """Round-off scale of dU/dt = -A R: |A| applied to the residual scale."""
-        return wa_apply_abs(self.mesh, self.c, self.residual_scale(U, t))
 
     def rk4_step(self, U, dt, t=0.0):
         return rk4_step(self.rhs, U, dt, t)

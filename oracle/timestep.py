@@ -1,6 +1,6 @@
 """Explicit time integration (oracle; test infrastructure only).
 
-Paper: Sec. 6 -- a four-stage, fourth-order Runge-Kutta scheme with an
+Paper: Sec. 7 (opening paragraph) -- a four-stage, fourth-order Runge-Kutta scheme with an
 adaptive step from the maximum wave speed and CFL = 0.1. Reading: the classical
 RK4 tableau; dt = CFL * dx / lambda_max with dx the mean node spacing
 (hi - lo) / (ne (p + 1)) of the first direction.

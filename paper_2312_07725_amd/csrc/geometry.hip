@@ -1,6 +1,6 @@
 // Mesh and metric setup kernel (untimed; runs once per context).
 //
-// Paper: Sec. 6, Eq. warped grid (nonsymmetric periodic warp of a uniform
+// Paper: Sec. 7 (opening paragraph), Eq. warped grid (nonsymmetric periodic warp of a uniform
 // hexahedral grid), Sec. 2.2 (covariant basis a_j, Jacobian J, cofactor matrix
 // C with C^T = J (J^Omega)^-1, built with the conservative curl form so that
 // the discrete GCL of Eq. GCL holds to round-off).

@@ -1,8 +1,10 @@
 // Device building blocks shared by the NSFR kernels (gfx950, FP64).
 //
-// Paper references: Sec. 2.1 (Euler system, entropy variables), Sec. 3.3
-// (entropy-conserving two-point flux of Chandrashekar in the variables rho, u,
-// beta = rho / (2p); the experiments of Sec. 6 use Ranocha's pressure fix).
+// Paper references: Sec. 2.1 (Euler system, entropy variables, Tadmor's
+// condition Eq. EC flux), Sec. 3.3 (entropy-conserving two-point flux of
+// Chandrashekar in the variables rho, u, beta = rho / (2p); the experiments of
+// Sec. 7 use Ranocha's pressure fix, stated in the opening paragraph of
+// Sec. 7), Sec. 6.1 (free-stream preservation).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -51,8 +53,56 @@ __device__ __forceinline__ Prim primitives(double r, double m1, double m2, doubl
     return q;
 }
 
+// Primitive variables of the forward kernels. The pressure is carried as its
+// difference pd = p - pref from a reference pressure pref that is constant over
+// the mesh for one evaluation.
+//
+// Why: in low-Mach flows p is a large constant plus a small variation (the
+// Mach-0.1 vortex has p ~ 71 varying by ~0.3), and the momentum residual is the
+// derivative of the variation. The constant part pref of the momentum flux
+// pref N sums to exactly zero at every node in exact arithmetic: its volume
+// and surface contributions are the free-stream residual of a constant state,
+// which vanishes by the discrete GCL and the single-valued face metric
+// (Sec. 6.1). Evaluated in FP64 it leaves round-off of order eps pref |C|,
+// which is most of the momentum residual's round-off. The forward kernels
+// therefore drop pref N from the momentum flux (keeping it in the energy
+// flux, where pref un does not cancel) and need pd accurate to eps |pd|, not
+// eps p: E - kin is formed with its exact rounding remainder (Fast2Sum, valid
+// since E >= kin when p > 0) and the product with gamma - 1 with its FMA
+// remainder, so that pd = (p_hi - pref) + p_lo loses nothing to the
+// cancellation of p_hi against pref.
+struct PrimR {
+    double rho, u, v, w, pd, beta;
+};
+
+__device__ __forceinline__ PrimR primitives_ref(double r, double m1, double m2, double m3, double E, double gm1,
+                                                double pref) {
+    PrimR q;
+    double ir = rcp_pos(r);
+    q.rho = r;
+    q.u = m1 * ir;
+    q.v = m2 * ir;
+    q.w = m3 * ir;
+    double kin = 0.5 * (m1 * q.u + m2 * q.v + m3 * q.w);
+    double s = E - kin;
+    double es = (E - s) - kin;                        // E - kin = s + es exactly
+    double ph = gm1 * s;
+    double pl = __builtin_fma(gm1, s, -ph) + gm1 * es; // gm1 (E - kin) = ph + pl
+    q.pd = (ph - pref) + pl;
+    q.beta = 0.5 * r * rcp_pos(ph);
+    return q;
+}
+
+// Reference pressure of one evaluation: the pressure at the first node of the
+// state array (plain FP64; every workgroup computes the identical value).
+__device__ __forceinline__ double reference_pressure(const double* U, int64_t SE, double gm1) {
+    const double r = U[0], m1 = U[SE], m2 = U[2 * SE], m3 = U[3 * SE], E = U[4 * SE];
+    return gm1 * (E - 0.5 * (m1 * m1 + m2 * m2 + m3 * m3) / r);
+}
+
 // Threshold on the squared relative jump below which the logarithmic mean
-// uses its series (same switch as the reference implementation).
+// uses its series: at u < 1e-4 the first omitted term of either series is
+// below u^4 / 9 < 1.2e-17 relative, under half an FP64 ulp.
 constexpr double LN_SWITCH = 1e-4;
 
 // Closed forms of the logarithmic mean and of its reciprocal, for the rare
@@ -92,16 +142,18 @@ __device__ __forceinline__ double inv_ln_mean(double a, double b, double rs) {
 
 // Entropy-conserving, kinetic-energy-preserving two-point flux f_s(A, B) . N
 // for the (unnormalised) direction N (Sec. 3.3; Tadmor's condition, Eq. EC
-// flux). VARIANT 0: momentum pressure is the arithmetic mean of p, energy flux
+// flux), with the constant pref N left out of the momentum flux (see PrimR).
+// VARIANT 0: momentum pressure is the arithmetic mean of p, energy flux
 // completed by Tadmor's condition (Ranocha's pressure fix); VARIANT 1: plain
-// Chandrashekar, pressure rho_avg / (2 beta_avg).
+// Chandrashekar, pressure rho_avg / (2 beta_avg), whose difference from pref
+// is the beta-weighted mean (beta_a pd_a + beta_b pd_b) / (beta_a + beta_b).
 //
 // Every expression is written so that swapping A and B leaves each rounded
 // operand unchanged or negates both factors of a product, so the result is
 // bitwise symmetric in (A, B) and odd in N even under FMA contraction.
 template <int VARIANT>
-__device__ __forceinline__ void ec_flux(const Prim& A, const Prim& B, double nx, double ny, double nz,
-                                        double c1, double F[5]) {
+__device__ __forceinline__ void ec_flux(const PrimR& A, const PrimR& B, double nx, double ny, double nz,
+                                        double c1, double pref, double F[5]) {
     double una = A.u * nx + A.v * ny + A.w * nz;
     double unb = B.u * nx + B.v * ny + B.w * nz;
     double un = 0.5 * (una + unb);
@@ -112,39 +164,40 @@ __device__ __forceinline__ void ec_flux(const Prim& A, const Prim& B, double nx,
     double um = 0.5 * (A.u + B.u), vm = 0.5 * (A.v + B.v), wm = 0.5 * (A.w + B.w);
     F[0] = frho;
     if (VARIANT == 0) {
-        double pm = 0.5 * (A.p + B.p);
+        double pm = 0.5 * (A.pd + B.pd);
         F[1] = um * frho + pm * nx;
         F[2] = vm * frho + pm * ny;
         F[3] = wm * frho + pm * nz;
         double uab = A.u * B.u + A.v * B.v + A.w * B.w;
-        double pe = pm * un - 0.25 * (A.p - B.p) * (una - unb);   // = (pa unb + pb una) / 2
+        double pe = (pm + pref) * un - 0.25 * (A.pd - B.pd) * (una - unb);   // = (pa unb + pb una) / 2
         F[4] = frho * (c1 * ibl + 0.5 * uab) + pe;
     } else {
-        double ph = 0.5 * (A.rho + B.rho) * rsb;
+        double ph = (__dmul_rn(A.beta, A.pd) + __dmul_rn(B.beta, B.pd)) * rsb;
         F[1] = um * frho + ph * nx;
         F[2] = vm * frho + ph * ny;
         F[3] = wm * frho + ph * nz;
         double qa = A.u * A.u + A.v * A.v + A.w * A.w;
         double qb = B.u * B.u + B.v * B.v + B.w * B.w;
-        F[4] = frho * (c1 * ibl - 0.25 * (qa + qb)) + (um * F[1] + vm * F[2] + wm * F[3]);
+        F[4] = frho * (c1 * ibl - 0.25 * (qa + qb)) + (um * F[1] + vm * F[2] + wm * F[3]) + pref * un;
     }
 }
 
 // Local Lax-Friedrichs term -|N| lambda_max (UB - UA) / 2 added to the
-// surface flux of the manufactured-solution runs.
-__device__ __forceinline__ void llf_add(const Prim& A, const Prim& B, const double UA[5], const double UB[5],
-                                        double nx, double ny, double nz, double gamma, double F[5]) {
+// surface flux of the manufactured-solution runs (the upwind dissipation of
+// Sec. 7.1, read as local Lax-Friedrichs on the conservative jumps).
+__device__ __forceinline__ void llf_add(const PrimR& A, const PrimR& B, const double UA[5], const double UB[5],
+                                        double nx, double ny, double nz, double gamma, double pref, double F[5]) {
     double nn = sqrt(nx * nx + ny * ny + nz * nz);
     double inn = 1.0 / nn;
     double una = fabs((A.u * nx + A.v * ny + A.w * nz) * inn);
     double unb = fabs((B.u * nx + B.v * ny + B.w * nz) * inn);
-    double ca = sqrt(gamma * A.p / A.rho), cb = sqrt(gamma * B.p / B.rho);
+    double ca = sqrt(gamma * (pref + A.pd) / A.rho), cb = sqrt(gamma * (pref + B.pd) / B.rho);
     double lam = fmax(una + ca, unb + cb);
     double k = 0.5 * lam * nn;
     for (int s = 0; s < 5; ++s) F[s] -= k * (UB[s] - UA[s]);
 }
 
-// Manufactured-solution source q(x, t) of Sec. 6.1.
+// Manufactured-solution source q(x, t) of Sec. 7.1.
 __device__ __forceinline__ void mms_source(double x, double y, double z, double t, double gamma, double q[5]) {
     const double pi = 3.141592653589793238462643383279502884;
     double c1 = pi / 10.0;
@@ -184,25 +237,21 @@ __device__ __forceinline__ void line_geometry(int dir, int l, int& base, int& st
     else { base = t1 + N * t2; stride = N * N; }
 }
 
-#ifndef NSFR_PAD
-#define NSFR_PAD 1
-#endif
-#ifndef NSFR_HALO_EARLY
-#define NSFR_HALO_EARLY 0
-#endif
-#ifndef NSFR_PREFETCH
-#define NSFR_PREFETCH 1
-#endif
-
-// LDS index of a node in the primitive block: one pad slot after every
-// xi-row when NSFR_PAD, so that the strided accesses of xi- and eta-lines
-// spread over the LDS banks.
+// LDS index of a node in a padded node block: one pad slot after every
+// xi-row, so that the strided accesses of eta- and zeta-lines spread over the
+// LDS banks. A padded block holds N^3 + N^2 doubles.
 template <int N>
 __device__ __forceinline__ int pad_node(int node) {
-    return NSFR_PAD ? node + node / N : node;
+    return node + node / N;
+}
+template <int N>
+constexpr int padded_block() {
+    return N * N * N + N * N;
 }
 
-// Primitive variables of a node from the LDS block [6][PN3] (padded index).
+// Primitive variables of a node from the LDS block [6][PN3] (padded index):
+// lds_prim for the adjoint (component 4 = p), lds_primr for the forward
+// kernels (component 4 = p - pref).
 template <int PN3>
 __device__ __forceinline__ Prim lds_prim(const double* L, int pn) {
     Prim q;
@@ -211,6 +260,17 @@ __device__ __forceinline__ Prim lds_prim(const double* L, int pn) {
     q.v = L[2 * PN3 + pn];
     q.w = L[3 * PN3 + pn];
     q.p = L[4 * PN3 + pn];
+    q.beta = L[5 * PN3 + pn];
+    return q;
+}
+template <int PN3>
+__device__ __forceinline__ PrimR lds_primr(const double* L, int pn) {
+    PrimR q;
+    q.rho = L[pn];
+    q.u = L[PN3 + pn];
+    q.v = L[2 * PN3 + pn];
+    q.w = L[3 * PN3 + pn];
+    q.pd = L[4 * PN3 + pn];
     q.beta = L[5 * PN3 + pn];
     return q;
 }

@@ -2,7 +2,8 @@
 // state checks and RK helpers. All reductions are two-pass with a fixed
 // combination order, so results are bitwise reproducible.
 //
-// Paper: Sec. 6 (adaptive step from the maximum wave speed), Sec. 5.2 / 5.3
+// Paper: Sec. 7 opening paragraph (adaptive step from the maximum wave
+// speed, CFL 0.1), Sec. 6.2 / 6.3
 // (global conservation and entropy conservation: sum_i R_i and
 // sum v . R vanish on a periodic mesh), Sec. 2.1 (entropy variables
 // v = [(gamma - s)/(gamma - 1) - beta |u|^2, 2 beta u, -2 beta],

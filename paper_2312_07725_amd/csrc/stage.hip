@@ -6,7 +6,8 @@
 // direction k is S1 (x) W (x) W, nonzero only between nodes of one k-line;
 // the surface-volume blocks cancel on collocated LGL nodes), Eq. weight-adj
 // ESFR mass (A = Pi~ (W J)^-1 Pi~^T, Pi~ a tensor product of rank-one
-// corrections of the identity), Sec. 6 (classical RK4).
+// corrections of the identity), Sec. 7 opening paragraph (four-stage,
+// fourth-order RK: read as classical RK4).
 //
 // Work decomposition: a workgroup owns `epb` elements. Every element has
 // 3 (p+1)^2 lines (p+1)^2 per direction; one thread owns one line. Its line's
@@ -57,7 +58,7 @@ __device__ __forceinline__ void line_pass(double* lr, int epb, int dir, const do
 template <int P, bool CWA, int VARIANT>
 __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0, double* lds) {
     constexpr int N = P + 1, N2 = N * N, N3 = N2 * N, LINES = 3 * N2;
-    constexpr int PN3 = NSFR_PAD ? N3 + N2 : N3;   // padded stride of a primitive component
+    constexpr int PN3 = padded_block<N>();          // padded stride of a primitive component
     constexpr int LDSE = 6 * PN3 + 9 * N3;          // LDS doubles per element
     const int tid = threadIdx.x, nth = blockDim.x;
     const int epb = A.epb;
@@ -65,6 +66,7 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
     const int64_t SE = E * N3;   // state stride
     const double gm1 = A.gamma - 1.0;
     const double c1 = A.c1;
+    const double pref = reference_pressure(A.Uin, SE, gm1);
 
     // ---- 1. primitives and metric columns of the workgroup's elements -> LDS
     for (int idx = tid; idx < epb * N3; idx += nth) {
@@ -72,13 +74,13 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
         int64_t e = e0 + el;
         if (e < E) {
             const double* U = A.Uin + e * N3 + node;
-            Prim q = primitives(U[0], U[SE], U[2 * SE], U[3 * SE], U[4 * SE], gm1);
+            PrimR q = primitives_ref(U[0], U[SE], U[2 * SE], U[3 * SE], U[4 * SE], gm1, pref);
             double* L = lds + el * LDSE + pad_node<N>(node);
             L[0] = q.rho;
             L[PN3] = q.u;
             L[2 * PN3] = q.v;
             L[3 * PN3] = q.w;
-            L[4 * PN3] = q.p;
+            L[4 * PN3] = q.pd;
             L[5 * PN3] = q.beta;
             const double* Cg = A.geo.Cline + e * N3 + node;   // same offset in line-major order
             double* Lc0 = lds + el * LDSE + 6 * PN3 + node;
@@ -107,41 +109,18 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
     for (int s = 0; s < 5; ++s)
 #pragma unroll
         for (int a = 0; a < N; ++a) R[s][a] = 0.0;
-#if NSFR_HALO_EARLY
-    // neighbour data across the two ends of the line, requested before the
-    // pair sweep so that their latency overlaps it
-    double Um5[5], Up5[5], cmn[3], cpn[3];
-    if (active) {
-        const int64_t em = neighbour(e, dir, -1, A.geo.nx, A.geo.ny, A.geo.nz);
-        const int64_t ep = neighbour(e, dir, +1, A.geo.nx, A.geo.ny, A.geo.nz);
-        const double* Cm = A.geo.Cline + ((int64_t)(dir * 3) * E + em) * N3 + (N - 1) * N2 + l;
-        const double* Cp = A.geo.Cline + ((int64_t)(dir * 3) * E + ep) * N3 + l;
-        const double* Ubm = A.Uin + em * N3 + base + (N - 1) * stride;
-        const double* Ubp = A.Uin + ep * N3 + base;
-#pragma unroll
-        for (int s = 0; s < 5; ++s) {
-            Um5[s] = Ubm[s * SE];
-            Up5[s] = Ubp[s * SE];
-        }
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            cmn[k] = Cm[k * SE];
-            cpn[k] = Cp[k * SE];
-        }
-    }
-#endif
     if (active) {
 #pragma unroll
         for (int a = 0; a < N - 1; ++a) {
-            const Prim qa = lds_prim<PN3>(Lp, pad_node<N>(base + a * stride));
+            const PrimR qa = lds_primr<PN3>(Lp, pad_node<N>(base + a * stride));
             const double cax = Lc[a * N2], cay = Lc[N3 + a * N2], caz = Lc[2 * N3 + a * N2];
 #pragma unroll
             for (int b = a + 1; b < N; ++b) {
-                const Prim qb = lds_prim<PN3>(Lp, pad_node<N>(base + b * stride));
+                const PrimR qb = lds_primr<PN3>(Lp, pad_node<N>(base + b * stride));
                 const double cbx = Lc[b * N2], cby = Lc[N3 + b * N2], cbz = Lc[2 * N3 + b * N2];
                 double F[5];
                 // direction C(a) + C(b) = 2 N; the 1/2 is folded into S1h
-                ec_flux<VARIANT>(qa, qb, cax + cbx, cay + cby, caz + cbz, c1, F);
+                ec_flux<VARIANT>(qa, qb, cax + cbx, cay + cby, caz + cbz, c1, pref, F);
                 const double sab = A.ops.S1h[a][b];
 #pragma unroll
                 for (int s = 0; s < 5; ++s) {
@@ -155,7 +134,6 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
         for (int side = 0; side < 2; ++side) {
             const int aown = side ? N - 1 : 0;
             const double sg = side ? 0.5 : -0.5;   // outward reference normal / 2
-#if !NSFR_HALO_EARLY
             const int anbr = side ? 0 : N - 1;
             const int64_t en = neighbour(e, dir, side ? 1 : -1, A.geo.nx, A.geo.ny, A.geo.nz);
             const double* Cn = A.geo.Cline + ((int64_t)(dir * 3) * E + en) * N3 + anbr * N2 + l;
@@ -164,24 +142,18 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
 #pragma unroll
             for (int s = 0; s < 5; ++s) Un5[s] = Ub[s * SE];
             const double cnx = Cn[0], cny = Cn[SE], cnz = Cn[2 * SE];
-#else
-            double Un5[5];
-#pragma unroll
-            for (int s = 0; s < 5; ++s) Un5[s] = side ? Up5[s] : Um5[s];
-            const double cnx = side ? cpn[0] : cmn[0], cny = side ? cpn[1] : cmn[1], cnz = side ? cpn[2] : cmn[2];
-#endif
-            const Prim qn = primitives(Un5[0], Un5[1], Un5[2], Un5[3], Un5[4], gm1);
-            const Prim qo = lds_prim<PN3>(Lp, pad_node<N>(base + aown * stride));
+            const PrimR qn = primitives_ref(Un5[0], Un5[1], Un5[2], Un5[3], Un5[4], gm1, pref);
+            const PrimR qo = lds_primr<PN3>(Lp, pad_node<N>(base + aown * stride));
             const double nx = sg * (Lc[aown * N2] + cnx), ny = sg * (Lc[N3 + aown * N2] + cny),
                          nz = sg * (Lc[2 * N3 + aown * N2] + cnz);
             double F[5];
-            ec_flux<VARIANT>(qo, qn, nx, ny, nz, c1, F);
+            ec_flux<VARIANT>(qo, qn, nx, ny, nz, c1, pref, F);
             if (A.diss) {
                 const double* Uo = A.Uin + e * N3 + base + aown * stride;
                 double Uo5[5];
 #pragma unroll
                 for (int s = 0; s < 5; ++s) Uo5[s] = Uo[s * SE];
-                llf_add(qo, qn, Uo5, Un5, nx, ny, nz, A.gamma, F);
+                llf_add(qo, qn, Uo5, Un5, nx, ny, nz, A.gamma, pref, F);
             }
 #pragma unroll
             for (int s = 0; s < 5; ++s) R[s][aown] += F[s];
@@ -214,7 +186,7 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
             }
         }
     };
-    if (NSFR_PREFETCH) fetch_epilogue();
+    fetch_epilogue();
     __syncthreads();   // all LDS line reads are done; the primitive block becomes the accumulator
 
     // ---- 4. sum the three directions in LDS ([epb][5][N3] at the element's
@@ -272,7 +244,6 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
         }
         return;
     }
-    if (!NSFR_PREFETCH) fetch_epilogue();
     if (CWA) {
         for (int d = 0; d < 3; ++d) {   // Pi~^T along xi, eta, zeta
             line_pass<N, PN3>(lr, epb, d, A.ops.pia, A.ops.pib);
@@ -326,213 +297,14 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
     }
 }
 
-// Node-centric variant of the stage: one thread per node. For each direction
-// in turn the thread evaluates the two-point flux of its node with every
-// other node of its line (each pair is thus evaluated twice, once per side)
-// and, at a line end, the face flux with the neighbour's trace. The residual
-// of the node accumulates in registers in a fixed order; the mass inverse
-// and the RK combination follow as in the line-centric body.
-template <int P, bool CWA, int VARIANT>
-__device__ __forceinline__ void stage_body_node(const StageArgs& A, const int64_t e0, double* lds) {
-    constexpr int N = P + 1, N2 = N * N, N3 = N2 * N;
-    constexpr int PN3 = NSFR_PAD ? N3 + N2 : N3;
-    constexpr int LDSE = 6 * PN3 + 9 * N3;
-    const int tid = threadIdx.x;
-    const int epb = A.epb;
-    const int64_t E = A.geo.E;
-    const int64_t SE = E * N3;
-    const double gm1 = A.gamma - 1.0;
-    const double c1 = A.c1;
-    const int mode = A.mode;
-
-    // ---- 1. own node: primitives and metric columns -> LDS
-    const int el = tid / N3;
-    const int node = tid - el * N3;
-    const int64_t e = e0 + el;
-    const bool active = el < epb && e < E;
-    const int64_t g = e * N3 + node;
-    const int pa = pad_node<N>(node);
-    Prim qa = {1.0, 0.0, 0.0, 0.0, 1.0, 0.5};
-    double U5[5] = {0, 0, 0, 0, 0};
-    if (active) {
-#pragma unroll
-        for (int s = 0; s < 5; ++s) U5[s] = A.Uin[s * SE + g];
-        qa = primitives(U5[0], U5[1], U5[2], U5[3], U5[4], gm1);
-        double* L = lds + el * LDSE + pa;
-        L[0] = qa.rho;
-        L[PN3] = qa.u;
-        L[2 * PN3] = qa.v;
-        L[3 * PN3] = qa.w;
-        L[4 * PN3] = qa.p;
-        L[5 * PN3] = qa.beta;
-        const double* Cg = A.geo.Cline + e * N3 + node;
-        double* Lc0 = lds + el * LDSE + 6 * PN3 + node;
-#pragma unroll
-        for (int k = 0; k < 9; ++k) Lc0[k * N3] = Cg[k * SE];
-    }
-    __syncthreads();
-
-    // ---- 2. volume pairs and face fluxes of the node, direction by direction
-    const double* Lp = lds + el * LDSE;
-    const int i = node % N, j = (node / N) % N, k = node / N2;
-    double R[5] = {0, 0, 0, 0, 0};
-    if (active) {
-#pragma unroll 1
-        for (int dir = 0; dir < 3; ++dir) {
-            const int a = dir == 0 ? i : (dir == 1 ? j : k);
-            const int l = dir == 0 ? j + N * k : (dir == 1 ? i + N * k : i + N * j);
-            const int stride = dir == 0 ? 1 : (dir == 1 ? N : N2);
-            const int base = node - a * stride;
-            const double* Lc = Lp + 6 * PN3 + 3 * dir * N3 + l;
-            const double cax = Lc[a * N2], cay = Lc[N3 + a * N2], caz = Lc[2 * N3 + a * N2];
-            double Rd[5] = {0, 0, 0, 0, 0};
-#pragma unroll 1
-            for (int b = 0; b < N; ++b) {
-                if (b == a) continue;
-                const Prim qb = lds_prim<PN3>(Lp, pad_node<N>(base + b * stride));
-                double F[5];
-                ec_flux<VARIANT>(qa, qb, cax + Lc[b * N2], cay + Lc[N3 + b * N2], caz + Lc[2 * N3 + b * N2], c1, F);
-                const double sab = A.ops.S1h[a][b];
-#pragma unroll
-                for (int s = 0; s < 5; ++s) Rd[s] = __builtin_fma(sab, F[s], Rd[s]);
-            }
-            if (a == 0 || a == N - 1) {
-                const int side = (a == N - 1) ? 1 : 0;
-                const int anbr = side ? 0 : N - 1;
-                const double sg = side ? 0.5 : -0.5;   // outward reference normal / 2
-                const int64_t en = neighbour(e, dir, side ? 1 : -1, A.geo.nx, A.geo.ny, A.geo.nz);
-                const double* Cn = A.geo.Cline + ((int64_t)(dir * 3) * E + en) * N3 + anbr * N2 + l;
-                const double* Ub = A.Uin + en * N3 + base + anbr * stride;
-                double Un5[5];
-#pragma unroll
-                for (int s = 0; s < 5; ++s) Un5[s] = Ub[s * SE];
-                const Prim qn = primitives(Un5[0], Un5[1], Un5[2], Un5[3], Un5[4], gm1);
-                const double nx = sg * (cax + Cn[0]), ny = sg * (cay + Cn[SE]), nz = sg * (caz + Cn[2 * SE]);
-                double F[5];
-                ec_flux<VARIANT>(qa, qn, nx, ny, nz, c1, F);
-                if (A.diss) llf_add(qa, qn, U5, Un5, nx, ny, nz, A.gamma, F);
-#pragma unroll
-                for (int s = 0; s < 5; ++s) Rd[s] += F[s];
-            }
-            const double wperp = A.ops.w[l % N] * A.ops.w[l / N];
-#pragma unroll
-            for (int s = 0; s < 5; ++s) R[s] = __builtin_fma(wperp, Rd[s], R[s]);
-        }
-    }
-
-    // ---- 3. source
-    double dt = 0.0, cstage = 0.0;
-    if (mode >= MODE_RK1) {
-        dt = *A.dt;
-        cstage = (mode == MODE_RK1) ? 0.0 : (mode == MODE_RK4 ? 1.0 : 0.5);
-    }
-    if (A.source && active) {
-        const double t = (A.tdev ? *A.tdev : A.t) + cstage * dt;
-        double qs[5];
-        const double* X = A.geo.X + g;
-        mms_source(X[0], X[SE], X[2 * SE], t, A.gamma, qs);
-        const double wj = 1.0 / A.geo.invWJ[g];
-#pragma unroll
-        for (int s = 0; s < 5; ++s) R[s] -= wj * qs[s];
-    }
-    if (mode == MODE_RESIDUAL) {
-        if (active) {
-#pragma unroll
-            for (int s = 0; s < 5; ++s) A.out[s * SE + g] = R[s];
-        }
-        return;
-    }
-
-    // ---- 4. mass inverse
-    double iw = 0.0, ua[5] = {0, 0, 0, 0, 0}, ub[5] = {0, 0, 0, 0, 0};
-    if (active) {
-        iw = A.geo.invWJ[g];
-        const double* pa_ = mode == MODE_RK1 ? A.Uin : A.acc;
-#pragma unroll
-        for (int s = 0; s < 5; ++s) {
-            if (mode >= MODE_RK1) ua[s] = pa_[s * SE + g];
-            if (mode == MODE_RK2 || mode == MODE_RK3) ub[s] = A.Un[s * SE + g];
-        }
-    }
-    double kv[5];
-    if (CWA) {
-        double* lr = lds;   // [epb][5][PN3], over the primitive block
-        __syncthreads();    // all pair reads of the primitive block are done
-        if (active) {
-#pragma unroll
-            for (int s = 0; s < 5; ++s) lr[(el * 5 + s) * PN3 + pa] = R[s];
-        }
-        __syncthreads();
-        for (int d = 0; d < 3; ++d) {   // Pi~^T along xi, eta, zeta
-            line_pass<N, PN3>(lr, epb, d, A.ops.pia, A.ops.pib);
-            __syncthreads();
-        }
-        if (active) {
-#pragma unroll
-            for (int s = 0; s < 5; ++s) lr[(el * 5 + s) * PN3 + pa] *= iw;
-        }
-        __syncthreads();
-        for (int d = 0; d < 3; ++d) {   // Pi~ along xi, eta, zeta
-            line_pass<N, PN3>(lr, epb, d, A.ops.pib, A.ops.pia);
-            __syncthreads();
-        }
-#pragma unroll
-        for (int s = 0; s < 5; ++s) kv[s] = active ? -lr[(el * 5 + s) * PN3 + pa] : 0.0;
-    } else {
-#pragma unroll
-        for (int s = 0; s < 5; ++s) kv[s] = -(R[s] * iw);
-    }
-    if (!active) return;
-
-    // ---- 5. RK combination
-#pragma unroll
-    for (int s = 0; s < 5; ++s) {
-        const double kk = kv[s];
-        const int64_t gi = s * SE + g;
-        switch (mode) {
-            case MODE_RHS: A.out[gi] = kk; break;
-            case MODE_RK1:
-                A.acc[gi] = __builtin_fma(dt / 6.0, kk, ua[s]);
-                A.out[gi] = __builtin_fma(0.5 * dt, kk, ua[s]);
-                break;
-            case MODE_RK2:
-                A.acc[gi] = __builtin_fma(dt / 3.0, kk, ua[s]);
-                A.out[gi] = __builtin_fma(0.5 * dt, kk, ub[s]);
-                break;
-            case MODE_RK3:
-                A.acc[gi] = __builtin_fma(dt / 3.0, kk, ua[s]);
-                A.out[gi] = __builtin_fma(dt, kk, ub[s]);
-                break;
-            default: A.out[gi] = __builtin_fma(dt / 6.0, kk, ua[s]); break;
-        }
-    }
-}
-
-#ifndef NSFR_NODE
-#define NSFR_NODE 0
-#endif
-#if NSFR_NODE
-#define NSFR_STAGE_BODY stage_body_node
-#else
-#define NSFR_STAGE_BODY stage_body
-#endif
-// threads per element of the stage kernel
-__host__ __device__ constexpr int stage_threads_per_elem(int n) { return NSFR_NODE ? n * n * n : 3 * n * n; }
-
-#ifndef NSFR_WAVES
-#define NSFR_WAVES 0
-#endif
-#if NSFR_WAVES
-#define NSFR_WAVES_ATTR __attribute__((amdgpu_waves_per_eu(NSFR_WAVES)))
-#else
-#define NSFR_WAVES_ATTR
-#endif
+// threads per element of the stage kernel: one per line
+__host__ __device__ constexpr int stage_threads_per_elem(int n) { return 3 * n * n; }
 
 template <int P, bool CWA, int VARIANT>
-__global__ __launch_bounds__(STAGE_BLOCK_MAX) NSFR_WAVES_ATTR void stage_kernel(StageArgs A) {
+__global__ __launch_bounds__(STAGE_BLOCK_MAX) void stage_kernel(StageArgs A) {
     extern __shared__ double lds[];
     const int g = xcd_remap(blockIdx.x, gridDim.x);
-    NSFR_STAGE_BODY<P, CWA, VARIANT>(A, (int64_t)g * A.epb, lds);
+    stage_body<P, CWA, VARIANT>(A, (int64_t)g * A.epb, lds);
 }
 
 // Persistent ensemble kernel: every workgroup walks the work list (flow,
@@ -551,7 +323,7 @@ __global__ __launch_bounds__(STAGE_BLOCK_MAX) void ensemble_kernel(const StageAr
         const StageArgs& A = table[f];
         switch (__builtin_amdgcn_readfirstlane(kinds[f])) {
 #define NSFR_CASE(P, C, V) \
-    case kind_code(P, C, V): NSFR_STAGE_BODY<P, C, V>(A, e0, lds); break;
+    case kind_code(P, C, V): stage_body<P, C, V>(A, e0, lds); break;
             NSFR_CASE(2, false, 0) NSFR_CASE(2, false, 1) NSFR_CASE(2, true, 0) NSFR_CASE(2, true, 1)
             NSFR_CASE(3, false, 0) NSFR_CASE(3, false, 1) NSFR_CASE(3, true, 0) NSFR_CASE(3, true, 1)
             NSFR_CASE(4, false, 0) NSFR_CASE(4, false, 1) NSFR_CASE(4, true, 0) NSFR_CASE(4, true, 1)
@@ -569,7 +341,7 @@ hipError_t launch_ensemble_stage(const StageArgs* table, const int2* items, int 
 }
 
 // LDS per element of the stage kernel (doubles): primitives (padded) + metric columns
-int stage_lds_doubles(int n) { return 6 * (n * n * n + (NSFR_PAD ? n * n : 0)) + 9 * n * n * n; }
+int stage_lds_doubles(int n) { return 6 * (n * n * n + n * n) + 9 * n * n * n; }
 
 int max_epb(int p) {
     const int n = p + 1;

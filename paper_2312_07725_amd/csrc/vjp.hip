@@ -84,86 +84,6 @@ __device__ __forceinline__ MeanGrad inv_ln_mean_grad(double a, double b, double 
     return r;
 }
 
-// Accumulate the primitive cotangents (rho, u, v, w, p, beta) of
-// dl . f_s(A, B; N) into gA and gB.
-template <int VARIANT>
-__device__ __forceinline__ void ec_flux_vjp(const Prim& A, const Prim& B, double nx, double ny, double nz, double c1,
-                                            const double dl[5], double gA[6], double gB[6]) {
-    const double una = A.u * nx + A.v * ny + A.w * nz;
-    const double unb = B.u * nx + B.v * ny + B.w * nz;
-    const double un = 0.5 * (una + unb);
-    const MeanGrad lr = ln_mean_grad(A.rho, B.rho);
-    const double rho_ln = lr.v, Lra = lr.da, Lrb = lr.db;
-    const double rsb = rcp_pos(A.beta + B.beta);
-    const MeanGrad lb = inv_ln_mean_grad(A.beta, B.beta, rsb);
-    const double ibl = lb.v, Iba = lb.da, Ibb = lb.db;
-    const double frho = rho_ln * un;
-    const double um = 0.5 * (A.u + B.u), vm = 0.5 * (A.v + B.v), wm = 0.5 * (A.w + B.w);
-    const double dE = dl[4];
-    double gfrho, gum, gvm, gwm, gun, guna = 0.0, gunb = 0.0, gibl;
-    double gua = 0.0, gva = 0.0, gwa = 0.0, gub = 0.0, gvb = 0.0, gwb = 0.0;
-    double gpa = 0.0, gpb = 0.0, gra = 0.0, grb = 0.0, gba = 0.0, gbb = 0.0;
-    if (VARIANT == 0) {
-        const double pm = 0.5 * (A.p + B.p);
-        const double uab = A.u * B.u + A.v * B.v + A.w * B.w;
-        const double X = c1 * ibl + 0.5 * uab;
-        gfrho = dl[0] + dl[1] * um + dl[2] * vm + dl[3] * wm + dE * X;
-        gum = dl[1] * frho;
-        gvm = dl[2] * frho;
-        gwm = dl[3] * frho;
-        const double gpm = dl[1] * nx + dl[2] * ny + dl[3] * nz + dE * un;
-        gpa += 0.5 * gpm;
-        gpb += 0.5 * gpm;
-        gibl = dE * frho * c1;
-        const double guab = 0.5 * dE * frho;
-        gua += guab * B.u; gva += guab * B.v; gwa += guab * B.w;
-        gub += guab * A.u; gvb += guab * A.v; gwb += guab * A.w;
-        // pe = pm un - (pa - pb)(una - unb) / 4
-        gun = gfrho * rho_ln + dE * pm;
-        const double gdp = -0.25 * dE * (una - unb);
-        const double gdun = -0.25 * dE * (A.p - B.p);
-        gpa += gdp;
-        gpb -= gdp;
-        guna += gdun;
-        gunb -= gdun;
-    } else {
-        const double ph = 0.5 * (A.rho + B.rho) * rsb;
-        const double qa = A.u * A.u + A.v * A.v + A.w * A.w;
-        const double qb = B.u * B.u + B.v * B.v + B.w * B.w;
-        const double X = c1 * ibl - 0.25 * (qa + qb);
-        const double Fm1 = um * frho + ph * nx, Fm2 = vm * frho + ph * ny, Fm3 = wm * frho + ph * nz;
-        const double g1 = dl[1] + dE * um, g2 = dl[2] + dE * vm, g3 = dl[3] + dE * wm;
-        gfrho = dl[0] + g1 * um + g2 * vm + g3 * wm + dE * X;
-        gum = g1 * frho + dE * Fm1;
-        gvm = g2 * frho + dE * Fm2;
-        gwm = g3 * frho + dE * Fm3;
-        const double gph = g1 * nx + g2 * ny + g3 * nz;
-        gra += 0.5 * rsb * gph;
-        grb += 0.5 * rsb * gph;
-        gba -= ph * rsb * gph;
-        gbb -= ph * rsb * gph;
-        const double gX = dE * frho;
-        gibl = gX * c1;
-        const double gq = -0.25 * gX;
-        gua += 2.0 * gq * A.u; gva += 2.0 * gq * A.v; gwa += 2.0 * gq * A.w;
-        gub += 2.0 * gq * B.u; gvb += 2.0 * gq * B.v; gwb += 2.0 * gq * B.w;
-        gun = gfrho * rho_ln;
-    }
-    // frho = rho_ln * un
-    const double grl = gfrho * un;
-    gra += grl * Lra;
-    grb += grl * Lrb;
-    gba += gibl * Iba;
-    gbb += gibl * Ibb;
-    // un = (una + unb) / 2, una = u_a . N
-    guna += 0.5 * gun;
-    gunb += 0.5 * gun;
-    gua += guna * nx + 0.5 * gum; gva += guna * ny + 0.5 * gvm; gwa += guna * nz + 0.5 * gwm;
-    gub += gunb * nx + 0.5 * gum; gvb += gunb * ny + 0.5 * gvm; gwb += gunb * nz + 0.5 * gwm;
-    gA[0] += gra; gA[1] += gua; gA[2] += gva; gA[3] += gwa; gA[4] += gpa; gA[5] += gba;
-    gB[0] += grb; gB[1] += gub; gB[2] += gvb; gB[3] += gwb; gB[4] += gpb; gB[5] += gbb;
-}
-
 // One-sided adjoint: accumulate only the primitive cotangents of A in
 // dl . f_s(A, B; N). Used by the node-centric reverse sweep, where each node
 // of a line differentiates its own side of every pair it belongs to.
@@ -288,7 +208,7 @@ __global__ __launch_bounds__(VJP_BLOCK_MAX) void mass_apply_kernel(StageArgs A, 
 // LDS doubles per element of the reverse sweep: primitives [6][PN3], metric
 // columns [9][N3] (line-major), mu [5][PN3].
 __host__ __device__ constexpr int vjp_lds_doubles(int n) {
-    return 11 * (n * n * n + (NSFR_PAD ? n * n : 0)) + 9 * n * n * n;
+    return 11 * (n * n * n + n * n) + 9 * n * n * n;
 }
 
 // Reverse sweep, node-centric. mu_given: mu is read from `mu` (c != 0);
@@ -304,7 +224,7 @@ template <int P, int VARIANT>
 __global__ __launch_bounds__(VJP_BLOCK_MAX) void vjp_kernel(StageArgs A, const double* lam, const double* mu,
                                                             int mu_given, double* g) {
     constexpr int N = P + 1, N2 = N * N, N3 = N2 * N;
-    constexpr int PN3 = NSFR_PAD ? N3 + N2 : N3;
+    constexpr int PN3 = padded_block<N>();
     constexpr int LDSE = vjp_lds_doubles(N);
     extern __shared__ double lds[];
     __shared__ double sS1h[N][N];

@@ -4,11 +4,11 @@ Shared by the tests, the benchmark and the smoke check; it holds no part of the
 numerical scheme itself, only the problem definitions of the paper's test
 cases evaluated at given node coordinates, and seeded random numbers.
 
-  * Taylor-Green vortex of Sec. 6.3: rho = 1, u = sin x cos y cos z,
+  * Taylor-Green vortex of Sec. 7.3: rho = 1, u = sin x cos y cos z,
     v = -cos x sin y cos z, w = 0, p = p0 + (cos2x cos2z + 2 cos2x + 2 cos2y
     + cos2y cos2z) / 16 with p0 = 1 / (gamma Mach^2) (Mach 0.1 gives the
     printed 100 / gamma), on [0, 2 pi]^3;
-  * manufactured solution of Sec. 6.1 at t = 0;
+  * manufactured solution of Sec. 7.1 at t = 0;
   * ensemble draws: elements per direction, degree and Mach per flow.
 
 Coordinates come in as a (3, ...) float64 tensor; states go out as (5, ...)

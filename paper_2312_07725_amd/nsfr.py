@@ -96,7 +96,7 @@ def _stream():
 
 
 def c_hu(p):
-    """FR parameter c_HU for degree p, computed by the library (Sec. 6.2)."""
+    """FR parameter c_HU for degree p, computed by the library (Sec. 7.2)."""
     out = c_double()
     _check(_lib().nsfr_c_hu(int(p), byref(out)), "nsfr_c_hu")
     return out.value

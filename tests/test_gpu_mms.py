@@ -1,4 +1,4 @@
-"""Order of accuracy on the GPU (manufactured-solution workload of Sec. 6.1):
+"""Order of accuracy on the GPU (manufactured-solution workload of Sec. 7.1):
 Euler with the manufactured source on the periodic warped mesh of [-1, 1]^3
 (beta = 1/50), entropy-conserving volume flux, EC + local Lax-Friedrichs
 surface flux, weight-adjusted inverse (c = 0 and c = c_HU), classical RK4 at

@@ -1,25 +1,27 @@
-"""GPU parity of the forward path against the CPU oracle (element by element).
+"""GPU parity of the forward path against the oracle (element by element).
 
-Tolerance: every entry differs from the oracle's by at most 1e-12 times the
-state's round-off scale, the largest over the mesh of the sum of the
-magnitudes of the terms the residual adds at a node (and of |A| applied to it
-for dU/dt). For rough states the plain max-normalised error
-is checked at 1e-12 as well. For smooth Mach-0.1 states max |R| is up to 1e5
-times smaller than the terms that cancel in it (the TGV density residual is
-pure truncation error), so normalising by it would measure the conditioning
-of the cancellation, not the arithmetic. Cases span p = 2..5,
-ragged element counts (so the last workgroup is partial), the single-element
-periodic mesh, both two-point flux variants, c = 0 and c = c_HU (weight-
-adjusted inverse with the rank-one FR projection), the dissipative surface
-flux with the manufactured source, and the full 16^3 TGV meshes.
+Criterion (oracle.parity): per state, the GPU's max-normalised error against
+the extended-precision evaluation of the oracle's definitions is at most
+max(1e-12, 2 x the FP64 oracle's own error against it). On rough states and
+small meshes the FP64 oracle is accurate to far below 1e-12, so the bar there
+is the plain 1e-12 relative one (and the rough cases are also compared with
+the FP64 oracle directly at 1e-12). The second term matters only where FP64
+itself cannot reach 1e-12: the smooth Mach-0.1 vortex on fine meshes, whose
+density residual is pure truncation error.
+
+Cases span p = 2..5, ragged element counts (so the last workgroup is partial),
+the single-element periodic mesh, both two-point flux variants, c = 0 and
+c = c_HU (weight-adjusted inverse with the rank-one FR projection), the
+dissipative surface flux with the manufactured source, and the full 16^3 TGV
+meshes (sampled elements) in the launch configuration the benchmark times.
 """
-import math
-
+import numpy as np
 import pytest
 import torch
 
 import oracle
-from gpu_helpers import assert_parity, assert_parity_scaled, cuda, make_pair, state, G
+from gpu_helpers import assert_ext, assert_parity, cuda, make_ext, make_pair, state, G
+from oracle import parity
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-12
@@ -27,16 +29,20 @@ TOL = 1e-12
 
 @pytest.mark.parametrize("p", [2, 3, 4, 5])
 def test_geometry(p, lib):
+    """Node coordinates, J and the metric cofactors against the extended
+    evaluation: no worse than twice the FP64 oracle's own error, with a floor
+    of 1e-14 (max-normalised per array), a hundred times tighter than the
+    residual bar because metric errors enter the residual amplified."""
     g, o = make_pair(p, (2, 3, 2), beta=0.2)
+    mx = make_ext(p, (2, 3, 2), beta=0.2).mesh
+    m64 = make_ext(p, (2, 3, 2), beta=0.2, dt=np.float64).mesh
     X = g.node_coords()
     C, J = g.geometry()
     torch.cuda.synchronize()
-    assert_parity(X.reshape(3, -1), o.mesh.X.reshape(3, -1), 1e-14, "coords")
-    assert_parity(J.reshape(1, -1), o.mesh.J.reshape(1, -1), 1e-13, "J")
-    # normalised by the largest metric entry: some entries vanish identically
-    # on coarse meshes and carry only round-off on either side
-    err = float((C.cpu() - o.mesh.C).abs().max() / o.mesh.C.abs().max())
-    assert err < 1e-12, err
+    f = lambda a: a.reshape(1, -1)   # noqa: E731
+    assert_ext(f(X), f(mx.X), [f(o.mesh.X), f(m64.X)], f"X p={p}", tol=1e-15)
+    assert_ext(f(J), f(mx.J), [f(o.mesh.J), f(m64.J)], f"J p={p}", tol=1e-14)
+    assert_ext(f(C), f(mx.C), [f(o.mesh.C), f(m64.C)], f"C p={p}", tol=1e-14)
 
 
 @pytest.mark.parametrize("p", [2, 3, 4, 5])
@@ -46,7 +52,9 @@ def test_residual_small(p, kind, flux, lib):
     g, o = make_pair(p, (3, 2, 4), beta=0.2, flux=flux)
     U = state(o, kind, seed=p)
     R = g.residual(cuda(U))
-    assert_parity_scaled(R, o.residual(U), o.residual_scale(U), TOL, f"residual p={p} {kind} flux={flux}")
+    ext = make_ext(p, (3, 2, 4), beta=0.2, flux=flux).residual(U.numpy())
+    x64 = make_ext(p, (3, 2, 4), beta=0.2, flux=flux, dt=np.float64).residual(U.numpy())
+    assert_ext(R, ext, [o.residual(U), x64], f"residual p={p} {kind} flux={flux}")
     if kind == "rough":
         assert_parity(R, o.residual(U), TOL, f"residual p={p} {kind} flux={flux}")
 
@@ -56,10 +64,14 @@ def test_residual_small(p, kind, flux, lib):
 def test_rhs_small(p, c, lib):
     cval = 0.0 if c == "0" else oracle.operators.c_hu(p)
     g, o = make_pair(p, (2, 3, 2), beta=0.2, c=cval)
+    xs = make_ext(p, (2, 3, 2), beta=0.2, c=cval)
+    x64 = make_ext(p, (2, 3, 2), beta=0.2, c=cval, dt=np.float64)
     U = state(o, "rough", seed=10 + p)
-    assert_parity(g.rhs(cuda(U)), o.rhs(U), TOL, f"rhs p={p} c={c}")
+    got = g.rhs(cuda(U))
+    assert_parity(got, o.rhs(U), TOL, f"rhs p={p} c={c}")
+    assert_ext(got, xs.rhs(U.numpy()), [o.rhs(U), x64.rhs(U.numpy())], f"rhs rough p={p} c={c}")
     Ut = state(o, "tgv")
-    assert_parity_scaled(g.rhs(cuda(Ut)), o.rhs(Ut), o.rhs_scale(Ut), TOL, f"rhs tgv p={p} c={c}")
+    assert_ext(g.rhs(cuda(Ut)), xs.rhs(Ut.numpy()), [o.rhs(Ut), x64.rhs(Ut.numpy())], f"rhs tgv p={p} c={c}")
 
 
 @pytest.mark.parametrize("p", [2, 3])
@@ -71,24 +83,50 @@ def test_single_element_periodic(p, lib):
 
 @pytest.mark.parametrize("p", [2, 4])
 def test_mms_source_and_dissipation(p, lib):
-    g, o = make_pair(p, (3, 2, 2), beta=0.02, lo=-1.0, hi=1.0, diss=1, source=1, c=oracle.operators.c_hu(p))
+    kw = dict(beta=0.02, lo=-1.0, hi=1.0, diss=1, source=1, c=oracle.operators.c_hu(p))
+    g, o = make_pair(p, (3, 2, 2), **kw)
+    xs = make_ext(p, (3, 2, 2), **kw)
+    x64 = make_ext(p, (3, 2, 2), dt=np.float64, **kw)
     U = state(o, "mms")
     t = 0.37
-    assert_parity_scaled(g.residual(cuda(U), t=t), o.residual(U, t), o.residual_scale(U, t), TOL, "mms residual")
-    assert_parity_scaled(g.rhs(cuda(U), t=t), o.rhs(U, t), o.rhs_scale(U, t), TOL, "mms rhs")
+    Un = U.numpy()
+    assert_ext(g.residual(cuda(U), t=t), xs.residual(Un, t), [o.residual(U, t), x64.residual(Un, t)], "mms residual")
+    assert_ext(g.rhs(cuda(U), t=t), xs.rhs(Un, t), [o.rhs(U, t), x64.rhs(Un, t)], "mms rhs")
 
 
 @pytest.mark.parametrize("p", [3, 4, 5])
 def test_full_size_tgv_16(p, lib):
     """16^3 warped TGV (beta = 1/5), c = c_HU, in the launch configuration the
-    benchmark times (default tile)."""
-    g, o = make_pair(p, 16, beta=0.2, c=oracle.operators.c_hu(p))
+    benchmark times (default tile): 96 sampled elements (seeded, including the
+    first and last, whose faces wrap around the periodic box) against the
+    extended evaluation; the FP64 references are the oracle's full-mesh rhs at
+    those elements and the FP64 coding of the extended module."""
+    c = oracle.operators.c_hu(p)
+    g, o = make_pair(p, 16, beta=0.2, c=c)
+    U = state(o, "tgv")
+    E = 16 ** 3
+    els = np.unique(np.concatenate([[0, E - 1], np.random.default_rng(p).choice(E, 94, replace=False)]))
+    xs = make_ext(p, 16, beta=0.2, c=c, elements=els)
+    x64 = make_ext(p, 16, beta=0.2, c=c, elements=els, dt=np.float64)
+    Un = U.numpy()
+    Et = torch.as_tensor(els)
+    got = g.rhs(cuda(U)).cpu()[:, Et]
+    assert_ext(got, xs.rhs(Un), [x64.rhs(Un), o.rhs(U)[:, Et]], f"16^3 p={p} rhs")
+    R = g.residual(cuda(U)).cpu()[:, Et]
+    assert_ext(R, xs.residual(Un), [x64.residual(Un), o.residual(U)[:, Et]], f"16^3 p={p} residual")
+
+
+def test_smoke_case_plain_bar(lib):
+    """The smoke workload (2 x 3 x 2 warped TGV, p = 3, c = c_HU) meets the
+    plain 1e-12 max-normalised bar against the extended evaluation in every
+    state, with no conditioning allowance."""
+    c = oracle.operators.c_hu(3)
+    g, o = make_pair(3, (2, 3, 2), beta=0.2, c=c)
     U = state(o, "tgv")
     got = g.rhs(cuda(U))
-    e = assert_parity_scaled(got, o.rhs(U), o.rhs_scale(U), TOL, f"16^3 p={p} rhs")
-    print(f"16^3 p={p}: scaled errors {e.tolist()}")
-    R = g.residual(cuda(U))
-    assert_parity_scaled(R, o.residual(U), o.residual_scale(U), TOL, f"16^3 p={p} residual")
+    e = parity.state_errors(got, make_ext(3, (2, 3, 2), beta=0.2, c=c).rhs(U.numpy()))
+    print("smoke case errors", e)
+    assert bool(np.all(e <= TOL)), e
 
 
 def test_tiles_and_determinism(lib):
@@ -110,7 +148,7 @@ def test_tiles_and_determinism(lib):
 
 @pytest.mark.parametrize("p", [2, 3, 4, 5])
 def test_invariants_on_gpu(p, lib):
-    """Sec. 5: free-stream preservation, global conservation and entropy
+    """Sec. 6.1-6.3: free-stream preservation, global conservation and entropy
     conservation of the GPU residual on the warped periodic mesh."""
     g, o = make_pair(p, (3, 3, 2), beta=0.2)
     Uc = state(o, "const")

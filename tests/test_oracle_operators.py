@@ -4,7 +4,7 @@ Each check is independent of how the oracle builds the operator: closed forms,
 exactness on polynomials, the SBP identity (Sec. 2.2, Eq. SBP; Sec. 3.3,
 Eq. SBP Qtilde), the p-th derivative of a Lagrange polynomial, the rank-one
 structure of the ESFR correction (Eq. Km) and of the FR projection (Eq. Fr
-projection), and the c_HU special case of Sec. 6.2.
+projection), and the c_HU special case of Sec. 7.2.
 """
 import json
 import math
@@ -81,7 +81,7 @@ def test_K_rank_one(p):
 
 @pytest.mark.parametrize("p", [2, 3, 4, 5])
 def test_c_hu_special_case(p):
-    """Sec. 6.2: with c_HU the modified mass of the exactly integrated Lagrange
+    """Sec. 7.2: with c_HU the modified mass of the exactly integrated Lagrange
     basis equals the LGL collocated mass. Closed form: W_LGL - M_exact is rank
     one, E_p lambda lambda^T, with E_p the LGL quadrature error of x^(2p), so
     c_HU = E_p / (2 (p!)^2)."""
