@@ -16,6 +16,8 @@ The modules are:
   mesh        warped periodic hexahedral mesh and conservative-curl metrics
   flux        Euler flux, entropy variables, the entropy-conserving two-point flux
   residual    NSFR residual: line-wise (sum-factorised) and dense (definition) forms
+  gl          NSFR with Gauss-Legendre (and overintegrated) quadrature: entropy
+              projection, hybrid surface-volume terms, weight-adjusted and exact mass
   mass        weight-adjusted and exact inverses of the FR-modified mass
   timestep    classical RK4, CFL time step
   problems    manufactured-solution state and source term
@@ -26,5 +28,5 @@ Functions whose result is not pinned by an independent test say "parity
 unpinned" in their docstring.
 """
 
-from . import operators, mesh, flux, residual, mass, timestep, problems, diagnostics, adjoint  # noqa: F401
+from . import operators, mesh, flux, residual, mass, timestep, problems, diagnostics, adjoint, gl  # noqa: F401
 from .scheme import Scheme  # noqa: F401
