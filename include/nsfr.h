@@ -69,7 +69,9 @@ typedef struct {
     int32_t surface_diss; /* 0: entropy-conserving surface flux; 1: plus local
                              Lax-Friedrichs dissipation                                  */
     int32_t source;       /* 0: none; 1: manufactured-solution source of Sec. 7.1        */
-    int32_t tile;         /* elements per workgroup of the stage kernel; 0 = default     */
+    int32_t tile;         /* elements per workgroup of the stage kernel, 3 (p+1)^2 threads
+                             (one per line) each, within 512 threads and 64 KB of LDS
+                             (p = 2..5: at most 17, 7, 4, 2); 0 = tuned default          */
 } nsfr_config;
 
 typedef struct nsfr_ctx nsfr_ctx;
@@ -163,6 +165,9 @@ typedef struct nsfr_ens nsfr_ens;
  * returned by nsfr_ens_offsets (n_flows + 1 entries, host). */
 nsfr_status nsfr_ens_create(const nsfr_config* cfgs, int32_t n_flows, void* hip_stream, nsfr_ens** out);
 nsfr_status nsfr_ens_destroy(nsfr_ens* ens);
+/* Stream (a hipStream_t, or null for the default stream) on which the
+ * ensemble's later calls enqueue their work. */
+nsfr_status nsfr_ens_set_stream(nsfr_ens* ens, void* hip_stream);
 nsfr_status nsfr_ens_offsets(const nsfr_ens* ens, int64_t* offsets_host);
 /* Residual / rhs of every flow at time t in one launch. */
 nsfr_status nsfr_ens_rhs(nsfr_ens* ens, const double* U, double* dUdt, double t);
@@ -172,8 +177,8 @@ nsfr_status nsfr_ens_rk4_step(nsfr_ens* ens, double* U, const double* dt_dev, do
 /* nsteps steps replayed from a HIP graph of one ensemble step. */
 nsfr_status nsfr_ens_rk4_run(nsfr_ens* ens, double* U, const double* dt_dev, double t,
                              int32_t nsteps, double* work);
-/* Elements per work item for degree p (2..5) used by the ensemble kernel;
- * epb = 0 restores the default. */
+/* Elements per work item for degree p (2..5) used by the ensemble kernel
+ * (the same bounds as the config's tile); epb = 0 restores the default. */
 nsfr_status nsfr_ens_set_tile(nsfr_ens* ens, int32_t p, int32_t epb);
 
 /* FR parameter c_HU (convention of Eq. Km) for degree p (2..5): the value for

@@ -26,6 +26,7 @@ struct nsfr_ctx {
     Ops ops;
     double* X = nullptr;       // [3][E][n3]
     double* Cline = nullptr;   // [3][3][E][n3] line-major per direction
+    int* nbr = nullptr;        // [6][E] face neighbours
     double* invWJ = nullptr;   // [E][n3]
     double* J = nullptr;       // [E][n3]
     double* wsR = nullptr;     // state-sized workspace
@@ -49,7 +50,7 @@ struct nsfr_ctx {
         }                                                                                     \
     } while (0)
 
-static nsfr_status bad(const char* msg) {
+static nsfr_status bad(const std::string& msg) {
     set_error(msg);
     return NSFR_EINVAL;
 }
@@ -88,6 +89,7 @@ static void free_ctx(nsfr_ctx* c) {
     for (double* b : bufs)
         if (b) (void)hipFree(b);
     if (c->cnt) (void)hipFree(c->cnt);
+    if (c->nbr) (void)hipFree(c->nbr);
     delete c;
 }
 
@@ -101,6 +103,7 @@ static StageArgs base_args(const nsfr_ctx* c) {
     a.geo.Cline = c->Cline;
     a.geo.invWJ = c->invWJ;
     a.geo.X = c->X;
+    a.geo.nbr = c->nbr;
     a.ops = c->ops;
     a.gamma = c->cfg.gamma;
     a.c1 = 1.0 / (2.0 * (c->cfg.gamma - 1.0));
@@ -163,6 +166,30 @@ nsfr_status nsfr_create(const nsfr_config* cfg, void* hip_stream, nsfr_ctx** out
     for (auto& al : allocs) {
         if (hipMalloc((void**)al.p, al.n * sizeof(double)) != hipSuccess) {
             set_error("hipMalloc failed for the context's device arrays");
+            free_ctx(c);
+            return NSFR_ENOMEM;
+        }
+    }
+    {   // face-neighbour table of the structured periodic box
+        const int nx = cfg->ne[0], ny = cfg->ne[1], nz = cfg->ne[2];
+        std::vector<int> nb((size_t)6 * c->E);
+        for (int ez = 0; ez < nz; ++ez)
+            for (int ey = 0; ey < ny; ++ey)
+                for (int ex = 0; ex < nx; ++ex) {
+                    const size_t e = ex + (size_t)nx * (ey + (size_t)ny * ez);
+                    const int xm = (ex + nx - 1) % nx, xp = (ex + 1) % nx;
+                    const int ym = (ey + ny - 1) % ny, yp = (ey + 1) % ny;
+                    const int zm = (ez + nz - 1) % nz, zp = (ez + 1) % nz;
+                    nb[0 * c->E + e] = xm + nx * (ey + ny * ez);
+                    nb[1 * c->E + e] = xp + nx * (ey + ny * ez);
+                    nb[2 * c->E + e] = ex + nx * (ym + ny * ez);
+                    nb[3 * c->E + e] = ex + nx * (yp + ny * ez);
+                    nb[4 * c->E + e] = ex + nx * (ey + ny * zm);
+                    nb[5 * c->E + e] = ex + nx * (ey + ny * zp);
+                }
+        if (hipMalloc((void**)&c->nbr, nb.size() * sizeof(int)) != hipSuccess ||
+            hipMemcpy(c->nbr, nb.data(), nb.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+            set_error("allocation or copy of the face-neighbour table failed");
             free_ctx(c);
             return NSFR_ENOMEM;
         }

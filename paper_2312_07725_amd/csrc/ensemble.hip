@@ -20,11 +20,10 @@ using namespace nsfr;
 
 namespace {
 constexpr int NMODES = 5;   // RK1..RK4, RHS
-constexpr int ENS_BLOCK = 512;
 
 int mode_slot(int mode) { return mode == MODE_RHS ? 4 : mode - MODE_RK1; }
 
-int default_ens_epb(int p) { return max_epb(p); }
+int default_ens_epb(int p) { return max_ensemble_epb(p); }
 }  // namespace
 
 struct nsfr_ens {
@@ -85,7 +84,7 @@ static nsfr_status build_items(nsfr_ens* s) {
             int cnt = (int)std::min<int64_t>(epb, E - e0);
             items.push_back({f, (int)e0, cnt * n3 * per_node_pairs});
         }
-        lds = std::max(lds, (size_t)epb * stage_lds_doubles(n) * sizeof(double));
+        lds = std::max(lds, stage_lds_bytes(c.p, epb));
     }
     std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) { return a.cost > b.cost; });
     std::vector<int2> h(items.size());
@@ -228,6 +227,15 @@ nsfr_status nsfr_ens_destroy(nsfr_ens* s) {
     return NSFR_OK;
 }
 
+nsfr_status nsfr_ens_set_stream(nsfr_ens* s, void* stream) {
+    if (!s) {
+        set_error("null ensemble");
+        return NSFR_EINVAL;
+    }
+    s->stream = (hipStream_t)stream;
+    return NSFR_OK;
+}
+
 nsfr_status nsfr_ens_offsets(const nsfr_ens* s, int64_t* offs) {
     if (!s || !offs) {
         set_error("null argument");
@@ -243,8 +251,8 @@ nsfr_status nsfr_ens_set_tile(nsfr_ens* s, int32_t p, int32_t epb) {
         return NSFR_EINVAL;
     }
     if (epb == 0) epb = default_ens_epb(p);
-    if (epb < 1 || epb > max_epb(p)) {
-        set_error("tile does not fit a 512-thread workgroup or the LDS budget");
+    if (epb < 1 || epb > max_ensemble_epb(p)) {
+        set_error("tile does not fit the ensemble workgroup (512 threads) or the LDS budget");
         return NSFR_EINVAL;
     }
     s->epb[p - 2] = epb;

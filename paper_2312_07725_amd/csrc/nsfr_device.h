@@ -215,16 +215,18 @@ __device__ __forceinline__ void mms_source(double x, double y, double z, double 
 
 // ---- indexing helpers shared by the element kernels
 
-// Periodic neighbour of element e across the face (dir, side = +-1).
-__device__ __forceinline__ int64_t neighbour(int64_t e, int dir, int side, int nx, int ny, int nz) {
-    int ex = (int)(e % nx);
-    int64_t r = e / nx;
-    int ey = (int)(r % ny);
-    int ez = (int)(r / ny);
-    if (dir == 0) ex = (ex + side + nx) % nx;
-    else if (dir == 1) ey = (ey + side + ny) % ny;
-    else ez = (ez + side + nz) % nz;
-    return ex + (int64_t)nx * (ey + (int64_t)ny * ez);
+// Periodic neighbour of element e across the face (dir, side = +-1); 32-bit
+// arithmetic (the library limits meshes to fewer than 2^31 elements).
+__device__ __forceinline__ int neighbour(int e, int dir, int side, int nx, int ny, int nz) {
+    const unsigned ue = (unsigned)e;
+    int ex = (int)(ue % (unsigned)nx);
+    const unsigned r = ue / (unsigned)nx;
+    int ey = (int)(r % (unsigned)ny);
+    int ez = (int)(r / (unsigned)ny);
+    if (dir == 0) ex = ex + side < 0 ? nx - 1 : (ex + side >= nx ? 0 : ex + side);
+    else if (dir == 1) ey = ey + side < 0 ? ny - 1 : (ey + side >= ny ? 0 : ey + side);
+    else ez = ez + side < 0 ? nz - 1 : (ez + side >= nz ? 0 : ez + side);
+    return ex + nx * (ey + ny * ez);
 }
 
 // Node index of position 0 and the node stride along line l of direction dir

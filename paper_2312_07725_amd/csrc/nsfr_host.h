@@ -27,6 +27,7 @@ struct Geo {
     const double* Cline;   // [3 dir][3 comp][E][n (position along line)][n^2 (line)]
     const double* invWJ;   // [E][n^3]
     const double* X;       // [3][E][n^3]
+    const int* nbr;        // [6][E]: periodic neighbour across face (dir, side), at dir * 2 + (side > 0)
 };
 
 enum StageMode : int {
@@ -61,7 +62,8 @@ hipError_t launch_geometry(int p, const Ops& ops, int nx, int ny, int nz, double
                            double l, double* X, double* Cline, double* invWJ, double* J, hipStream_t s);
 hipError_t launch_stage(int p, bool cwa, int variant, const StageArgs& a, hipStream_t s);
 int default_epb(int p);
-int stage_lds_doubles(int n);
+size_t stage_lds_bytes(int p, int epb);
+int max_ensemble_epb(int p);
 int max_epb(int p);
 hipError_t launch_geometry_export(int p, int64_t E, const double* Cline, double* C, hipStream_t s);
 hipError_t launch_max_wavespeed(int64_t nnodes, const double* U, double gamma, double* partial, int nblk,

@@ -70,9 +70,17 @@ void build_ops(int p, double c, Ops& ops, HostOps& h) {
         }
         h.D[i][i] = diag;
     }
-    // skew volume operator S1 = W D - D^T W
-    for (int i = 0; i < n; ++i)
-        for (int j = 0; j < n; ++j) h.S1[i][j] = h.w[i] * h.D[i][j] - h.D[j][i] * h.w[j];
+    // skew volume operator S1 = W D - D^T W, made exactly antisymmetric (the
+    // kernels rely on S1[b][a] = -S1[a][b] bitwise for discrete conservation)
+    for (int i = 0; i < n; ++i) {
+        h.S1[i][i] = 0.0;
+        for (int j = i + 1; j < n; ++j) {
+            const double wd = h.w[i] * h.D[i][j];
+            const double dw = h.D[j][i] * h.w[j];
+            h.S1[i][j] = wd - dw;
+            h.S1[j][i] = -h.S1[i][j];
+        }
+    }
     // d = p! lambda; FR projection in rank-one form
     double fact = 1.0;
     for (int k = 2; k <= p; ++k) fact *= k;

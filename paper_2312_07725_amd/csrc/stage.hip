@@ -135,7 +135,7 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
             const int aown = side ? N - 1 : 0;
             const double sg = side ? 0.5 : -0.5;   // outward reference normal / 2
             const int anbr = side ? 0 : N - 1;
-            const int64_t en = neighbour(e, dir, side ? 1 : -1, A.geo.nx, A.geo.ny, A.geo.nz);
+            const int64_t en = A.geo.nbr[(int64_t)(2 * dir + side) * E + e];
             const double* Cn = A.geo.Cline + ((int64_t)(dir * 3) * E + en) * N3 + anbr * N2 + l;
             const double* Ub = A.Uin + en * N3 + base + anbr * stride;
             double Un5[5];
@@ -341,7 +341,9 @@ hipError_t launch_ensemble_stage(const StageArgs* table, const int2* items, int 
 }
 
 // LDS per element of the stage kernel (doubles): primitives (padded) + metric columns
-int stage_lds_doubles(int n) { return 6 * (n * n * n + n * n) + 9 * n * n * n; }
+static int stage_lds_doubles(int n) { return 6 * (n * n * n + n * n) + 9 * n * n * n; }
+
+size_t stage_lds_bytes(int p, int epb) { return (size_t)epb * stage_lds_doubles(p + 1) * sizeof(double); }
 
 int max_epb(int p) {
     const int n = p + 1;
@@ -349,6 +351,9 @@ int max_epb(int p) {
     const int by_lds = (int)(65536 / (stage_lds_doubles(n) * sizeof(double)));
     return by_threads < by_lds ? by_threads : by_lds;
 }
+
+// the ensemble kernel runs workgroups of STAGE_BLOCK_MAX threads too
+int max_ensemble_epb(int p) { return max_epb(p); }
 
 int default_epb(int p) {
     switch (p) {

@@ -59,6 +59,7 @@ _SIGS = {
     "nsfr_kinetic_energy": [c_void_p, c_void_p, c_void_p, c_void_p],
     "nsfr_ens_create": [POINTER(Config), c_int32, c_void_p, POINTER(c_void_p)],
     "nsfr_ens_destroy": [c_void_p],
+    "nsfr_ens_set_stream": [c_void_p, c_void_p],
     "nsfr_ens_offsets": [c_void_p, POINTER(c_int64)],
     "nsfr_ens_rhs": [c_void_p, c_void_p, c_void_p, c_double],
     "nsfr_ens_rk4_step": [c_void_p, c_void_p, c_void_p, c_double, c_void_p],
@@ -310,6 +311,9 @@ class Ensemble:
             raise ValueError(f"{name} must be contiguous with {n} elements")
         return c_void_p(t.data_ptr())
 
+    def _sync_stream(self):
+        _check(_lib().nsfr_ens_set_stream(self._h, _stream()), "nsfr_ens_set_stream")
+
     def flow_view(self, packed, i):
         c = self.configs[i]
         n = c.p + 1
@@ -318,18 +322,21 @@ class Ensemble:
 
     def rhs(self, U, out=None, t=0.0):
         out = self.empty() if out is None else out
+        self._sync_stream()
         _check(_lib().nsfr_ens_rhs(self._h, self._a(U, self.total, "U"), self._a(out, self.total, "dUdt"), float(t)),
                "nsfr_ens_rhs")
         return out
 
     def rk4_step(self, U, dt, t=0.0, work=None):
         work = self.empty(3) if work is None else work
+        self._sync_stream()
         _check(_lib().nsfr_ens_rk4_step(self._h, self._a(U, self.total, "U"), self._a(dt, len(self.configs), "dt"),
                                         float(t), self._a(work, 3 * self.total, "work")), "nsfr_ens_rk4_step")
         return U
 
     def rk4_run(self, U, dt, nsteps, t=0.0, work=None):
         work = self.empty(3) if work is None else work
+        self._sync_stream()
         _check(_lib().nsfr_ens_rk4_run(self._h, self._a(U, self.total, "U"), self._a(dt, len(self.configs), "dt"),
                                        float(t), int(nsteps), self._a(work, 3 * self.total, "work")),
                "nsfr_ens_rk4_run")
