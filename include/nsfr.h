@@ -112,6 +112,20 @@ nsfr_status nsfr_rhs(nsfr_ctx* ctx, const double* U, double* dUdt, double t);
  * doubles). t is the time at the start of the step (source only). */
 nsfr_status nsfr_rk4_step(nsfr_ctx* ctx, double* U, const double* dt_dev, double t, double* work);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the RK4
+ * step of nsfr_rk4_step without the work argument. Its three stage arrays
+ * live in a workspace compiled into the library, NSFR_STATIC_MAX_NODES nodes
+ * (120 MiB) per GPU, held by each GPU the library runs on until the process
+ * ends; meshes with more than NSFR_STATIC_MAX_NODES nodes (E (p+1)^3) are
+ * rejected with NSFR_EINVAL before any launch. The call allocates nothing.
+ * Every call on one GPU shares that workspace: calls that overlap on one GPU
+ * (other streams, other contexts, other threads) race and must be ordered by
+ * the caller. Nothing in the workspace needs to start at zero (each stage
+ * writes every value it later reads). */
+#define NSFR_STATIC_MAX_NODES (1 << 20)
+nsfr_status nsfr_rk4_step_static(nsfr_ctx* ctx, double* U, const double* dt_dev, double t);
+
 /* nsteps RK4 steps replayed from a HIP graph of one step (the four stage
  * kernels). The time is read from and advanced in device memory t_dev (one
  * double) by dt each step; t_dev may be NULL when the configuration has no

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -119,6 +120,31 @@ static nsfr_status stage(nsfr_ctx* c, StageArgs& a) {
         set_error(std::string("stage kernel launch: ") + hipGetErrorString(e));
         return NSFR_EHIP;
     }
+    return NSFR_OK;
+}
+
+// Workspace of nsfr_rk4_step_static: three state-sized arrays of up to
+// NSFR_STATIC_MAX_NODES nodes, one copy per GPU (device global). Host code
+// never uses the symbol itself: its device address is looked up once per
+// device (with that device current) and kept in g_static_ws.
+static __device__ __align__(256) double scratch[(size_t)15 * NSFR_STATIC_MAX_NODES];
+
+static std::mutex g_static_mu;
+static double* g_static_ws[64] = {};
+
+static nsfr_status static_workspace(int dev, double** out) {
+    if (dev < 0 || dev >= 64) return bad("device index out of range for the static workspace");
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (!g_static_ws[dev]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_error(std::string("hipGetSymbolAddress(static workspace): ") + hipGetErrorString(e));
+            return NSFR_EHIP;
+        }
+        g_static_ws[dev] = static_cast<double*>(p);
+    }
+    *out = g_static_ws[dev];
     return NSFR_OK;
 }
 
@@ -310,6 +336,19 @@ nsfr_status nsfr_rk4_step(nsfr_ctx* c, double* U, const double* dt, double t, do
     nsfr_status st = use_device(c);
     if (st) return st;
     return rk4_enqueue(c, U, dt, t, nullptr, work);
+}
+
+nsfr_status nsfr_rk4_step_static(nsfr_ctx* c, double* U, const double* dt, double t) {
+    if (!c || !aligned(U) || !aligned(dt)) return bad("null or misaligned argument");
+    const int64_t nodes = c->E * (int64_t)c->n3;
+    if (nodes > NSFR_STATIC_MAX_NODES)
+        return bad("nsfr_rk4_step_static: the mesh has " + std::to_string(nodes) +
+                   " nodes; the static workspace holds at most " + std::to_string(NSFR_STATIC_MAX_NODES));
+    nsfr_status st = use_device(c);
+    if (st) return st;
+    double* ws = nullptr;
+    if ((st = static_workspace(c->dev, &ws))) return st;
+    return rk4_enqueue(c, U, dt, t, nullptr, ws);
 }
 
 nsfr_status nsfr_rk4_run(nsfr_ctx* c, double* U, const double* dt, double* tdev, int32_t nsteps, double* work) {

@@ -49,6 +49,7 @@ _SIGS = {
     "nsfr_residual": [c_void_p, c_void_p, c_void_p, c_double],
     "nsfr_rhs": [c_void_p, c_void_p, c_void_p, c_double],
     "nsfr_rk4_step": [c_void_p, c_void_p, c_void_p, c_double, c_void_p],
+    "nsfr_rk4_step_static": [c_void_p, c_void_p, c_void_p, c_double],
     "nsfr_rk4_run": [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_void_p],
     "nsfr_max_wavespeed": [c_void_p, c_void_p, c_void_p],
     "nsfr_cfl_dt": [c_void_p, c_void_p, c_double, c_void_p],
@@ -207,6 +208,14 @@ class NSFR:
         self._sync_stream()
         _check(_lib().nsfr_rk4_step(self._ctx, self._st(U, "U"), self._arr(dt, 1, "dt"), float(t),
                                     self._arr(work, 15 * self.n_nodes, "work")), "nsfr_rk4_step")
+        return U
+
+    def rk4_step_static(self, U, dt, t=0.0):
+        """nsfr_rk4_step without a work argument: the stage arrays live in the
+        library's per-GPU static workspace (no allocation by the library)."""
+        self._sync_stream()
+        _check(_lib().nsfr_rk4_step_static(self._ctx, self._st(U, "U"), self._arr(dt, 1, "dt"), float(t)),
+               "nsfr_rk4_step_static")
         return U
 
     def rk4_run(self, U, dt, t_dev, nsteps, work=None):
