@@ -13,7 +13,8 @@
  *     metric-split reference two-point flux (Eq. NSFR), evaluated line by
  *     line (Sec. 5, sum-factorised Hadamard product);
  *   - surface term: the same two-point flux (optionally plus local
- *     Lax-Friedrichs dissipation) at shared face nodes, lifted by the
+ *     Lax-Friedrichs or entropy-stable Roe-type matrix dissipation) at shared
+ *     face nodes, lifted by the
  *     FR-modified mass (Eq. NSFR, last term; Sec. 3.2);
  *   - mass: weight-adjusted inverse Pi~ (W J)^-1 Pi~^T of the FR-modified mass
  *     (Eq. weight-adj ESFR mass, Eq. Fr projection);
@@ -67,7 +68,9 @@ typedef struct {
     int32_t flux;         /* 0: Chandrashekar flux with Ranocha's pressure fix (arithmetic
                              mean pressure); 1: plain Chandrashekar flux                 */
     int32_t surface_diss; /* 0: entropy-conserving surface flux; 1: plus local
-                             Lax-Friedrichs dissipation                                  */
+                             Lax-Friedrichs dissipation on the conservative jump; 2: plus
+                             the entropy-stable Roe-type matrix dissipation on the jump
+                             of the entropy variables (Sec. 6.3, Sec. 7.1)               */
     int32_t source;       /* 0: none; 1: manufactured-solution source of Sec. 7.1        */
     int32_t tile;         /* elements per workgroup of the stage kernel, 3 (p+1)^2 threads
                              (one per line) each, within 512 threads and 64 KB of LDS
@@ -174,7 +177,8 @@ nsfr_status nsfr_check_state(nsfr_ctx* ctx, const double* U, int32_t* bad_host);
 /* ---- ensembles of independent flows, one launch per RK stage ------------ */
 typedef struct nsfr_ens nsfr_ens;
 
-/* n_flows configurations (any mix of p and ne). The packed state is the
+/* n_flows configurations (any mix of p, ne, c and flux; surface_diss and
+ * source must be 0, else NSFR_ENOTSUP). The packed state is the
  * concatenation of the flows' state arrays; offsets (in doubles) are
  * returned by nsfr_ens_offsets (n_flows + 1 entries, host). */
 nsfr_status nsfr_ens_create(const nsfr_config* cfgs, int32_t n_flows, void* hip_stream, nsfr_ens** out);

@@ -239,6 +239,51 @@ def llf(Ua, Ub, N, gamma):
     return -lam * nn * (Ub - Ua) / 2
 
 
+def _entropy_vars(U, gamma):
+    rho, (u, v, w), p, beta = primitives(U, gamma)
+    s = np.log(p) - gamma * np.log(rho)
+    return np.stack([(gamma - s) / (gamma - 1) - beta * (u * u + v * v + w * w),
+                     2 * beta * u, 2 * beta * v, 2 * beta * w, -2 * beta])
+
+
+def roe(Ua, Ub, N, gamma):
+    """Entropy-stable Roe-type matrix dissipation -|N| R |Lambda| T R^T [v] / 2
+    at the averaged state (rho_ln, mean velocity, mean(rho) / (2 mean(beta))),
+    written out as the rank-one sum over the acoustic and entropy waves plus
+    the shear block p |u.n| (I - n n^T) acting on w = [v]_m + u [v]_E."""
+    ra, ua, pa, ba = primitives(Ua, gamma)
+    rb, ub, pb, bb = primitives(Ub, gamma)
+    rho = ln_mean(ra, rb)
+    u = [(ua[k] + ub[k]) / 2 for k in range(3)]
+    p = (ra + rb) / (2 * (ba + bb))
+    nn = np.sqrt(N[0] ** 2 + N[1] ** 2 + N[2] ** 2)
+    n = [N[k] / nn for k in range(3)]
+    a = np.sqrt(gamma * p / rho)
+    q2 = u[0] ** 2 + u[1] ** 2 + u[2] ** 2
+    h = a * a / (gamma - 1) + q2 / 2
+    un = u[0] * n[0] + u[1] * n[1] + u[2] * n[2]
+    dv = _entropy_vars(Ub, gamma) - _entropy_vars(Ua, gamma)
+    one = np.ones_like(rho)
+    waves = []
+    for sg in (-1, 1):
+        r = [one, u[0] + sg * a * n[0], u[1] + sg * a * n[1], u[2] + sg * a * n[2], h + sg * a * un]
+        waves.append((r, np.abs(un + sg * a) * rho / (2 * gamma)))
+    waves.append(([one, u[0], u[1], u[2], q2 / 2], np.abs(un) * (gamma - 1) * rho / gamma))
+    D = np.zeros_like(Ua)
+    for r, sc in waves:
+        proj = sum(r[i] * dv[i] for i in range(5)) * sc
+        for i in range(5):
+            D[i] = D[i] + proj * r[i]
+    w = [dv[1 + k] + u[k] * dv[4] for k in range(3)]
+    wn = w[0] * n[0] + w[1] * n[1] + w[2] * n[2]
+    Pw = [w[k] - wn * n[k] for k in range(3)]
+    sc = np.abs(un) * p
+    for k in range(3):
+        D[1 + k] = D[1 + k] + sc * Pw[k]
+    D[4] = D[4] + sc * (u[0] * Pw[0] + u[1] * Pw[1] + u[2] * Pw[2])
+    return -nn * D / 2
+
+
 def mms_source(X, t, gamma, dt=LD):
     pi = _pi(dt)
     g = dt(gamma)
@@ -278,7 +323,7 @@ class SchemeX:
         self.p, self.n = p, p + 1
         self.gamma = dt(gamma)
         self.variant = variant
-        self.dissipation, self.source = bool(dissipation), bool(source)
+        self.dissipation, self.source = int(dissipation), bool(source)
         self.Pi = Ops1D(p, c, dt).Pi
         self.tloc = self.mesh.loc[self.target]
 
@@ -317,8 +362,10 @@ class SchemeX:
                 Cb = self._lines(m.C[:, k][:, m.loc[nb]], k)[..., an]
                 N = [side * (Co[i] + Cb[i]) / 2 for i in range(3)]
                 fs = ec_flux(Uo, Ub, N, g, self.variant)
-                if self.dissipation:
+                if self.dissipation == 1:
                     fs = fs + llf(Uo, Ub, N, g)
+                elif self.dissipation == 2:
+                    fs = fs + roe(Uo, Ub, N, g)
                 Rk[..., ao] = Rk[..., ao] + Wf * fs
             R = R + self._back(Rk, k)
         if self.source:

@@ -151,6 +151,71 @@ def llf_dissipation(Ua, Ub, N, gamma):
     return -0.5 * lam * nn * (Ub - Ua)
 
 
+def roe_dissipation(Ua, Ub, N, gamma):
+    """Entropy-stable Roe-type matrix dissipation on the jump of the entropy
+    variables, -|N| R |Lambda| T R^T (v_b - v_a) / 2, added to the EC surface
+    flux (Sec. 6.3: Roe's dissipation recast with entropy-variable jumps is
+    provably entropy dissipative; Sec. 7.1: the manufactured-solution runs add
+    Roe dissipation to the EC flux).
+
+    Reading: R, |Lambda| and T are the eigenvectors, the absolute eigenvalues
+    and Barth's eigenvector scaling (R T R^T = du/dv) of the Euler flux
+    Jacobian in the direction n = N / |N|, all evaluated at one averaged state
+    (rho_ln, arithmetic-mean velocity, p = mean(rho) / (2 mean(beta))).
+    Because R T R^T is symmetric positive definite and |Lambda| >= 0, the
+    entropy production -(v_b - v_a) . term is never positive.
+
+      waves n -+ a:  r = [1, u -+ a n, h -+ a u.n],  T = rho / (2 gamma)
+      entropy wave:  r = [1, u, |u|^2 / 2],          T = (gamma - 1) rho / gamma
+      shear waves:   sum_t T r r^T dv with T = p, r = [0, t, u.t], t _|_ n,
+                     = p [0, P w, u . P w], P = I - n n^T, w = dv_m + u dv_E
+    with h = a^2 / (gamma - 1) + |u|^2 / 2, a = sqrt(gamma p / rho). Real
+    tensors only."""
+    ra, va, pa, ba = primitives(Ua, gamma)
+    rb, vb, pb, bb = primitives(Ub, gamma)
+    rho = ln_mean(ra, rb)
+    u = [0.5 * (va[k] + vb[k]) for k in range(3)]
+    p = 0.5 * (ra + rb) / (ba + bb)
+    nn = torch.sqrt(N[0] ** 2 + N[1] ** 2 + N[2] ** 2)
+    n = [N[k] / nn for k in range(3)]
+    a = torch.sqrt(gamma * p / rho)
+    q2 = u[0] ** 2 + u[1] ** 2 + u[2] ** 2
+    h = a * a / (gamma - 1.0) + 0.5 * q2
+    un = u[0] * n[0] + u[1] * n[1] + u[2] * n[2]
+    dv = entropy_variables(Ub, gamma) - entropy_variables(Ua, gamma)
+    out = torch.zeros_like(Ua)
+    # acoustic waves
+    for sgn in (-1.0, 1.0):
+        r = [torch.ones_like(rho)] + [u[k] + sgn * a * n[k] for k in range(3)] + [h + sgn * a * un]
+        c = sum(r[i] * dv[i] for i in range(5)) * (un + sgn * a).abs() * rho / (2.0 * gamma)
+        out = out + torch.stack([c * r[i] for i in range(5)])
+    # entropy wave
+    r = [torch.ones_like(rho)] + u + [0.5 * q2]
+    c = sum(r[i] * dv[i] for i in range(5)) * un.abs() * (gamma - 1.0) * rho / gamma
+    out = out + torch.stack([c * r[i] for i in range(5)])
+    # shear waves
+    w = [dv[1 + k] + u[k] * dv[4] for k in range(3)]
+    wn = w[0] * n[0] + w[1] * n[1] + w[2] * n[2]
+    Pw = [w[k] - wn * n[k] for k in range(3)]
+    c = un.abs() * p
+    uPw = u[0] * Pw[0] + u[1] * Pw[1] + u[2] * Pw[2]
+    out = out + torch.stack([torch.zeros_like(rho), c * Pw[0], c * Pw[1], c * Pw[2], c * uPw])
+    return -0.5 * nn * out
+
+
+def surface_dissipation(kind, gamma):
+    """The dissipation term added to the EC surface flux: None for kind 0 /
+    False, local Lax-Friedrichs for kind 1 / True / "llf", the entropy-stable
+    Roe-type matrix dissipation for kind 2 / "roe"."""
+    if kind is None or kind is False or kind == 0:
+        return None
+    if kind is True or kind == 1 or kind == "llf":
+        return lambda a, b, N: llf_dissipation(a, b, N, gamma)
+    if kind == 2 or kind == "roe":
+        return lambda a, b, N: roe_dissipation(a, b, N, gamma)
+    raise ValueError(f"unknown surface dissipation {kind!r}")
+
+
 def max_wavespeed(U, gamma):
     """max over nodes of |u| + sqrt(gamma p / rho) (Sec. 7 opening paragraph: adaptive step)."""
     rho, vel, p, _ = primitives(U, gamma)

@@ -246,7 +246,7 @@ def residual(gm, ops, U, gamma, variant=0, dissipation=False, two_point=None):
     F(x, y) = f_s(x, y) . (C(x) + C(y)) / 2 with column k of C, and
       R_f    += w_perp n^r . f*   (the surface term of Eq. NSFR)."""
     tp = two_point or (lambda a, b, N: fx.ec_flux(a, b, N, gamma, variant))
-    diss = (lambda a, b, N: fx.llf_dissipation(a, b, N, gamma)) if dissipation else None
+    diss = fx.surface_dissipation(dissipation, gamma)
     _, uv, uf = entropy_projection(ops, U, gamma)
     wq = ops.wq
     wperp = wq[:, None] * wq[None, :]                 # tangential weights (t2, t1)
@@ -352,7 +352,7 @@ def residual_definition(gm, ops, U, gamma, variant=0, dissipation=False, two_poi
     with every state, cofactor and projection formed by dense matrices. Small
     meshes only (memory grows as E (Nq^3 + 6 Nq^2)^2)."""
     tp = two_point or (lambda a, b, N: fx.ec_flux(a, b, N, gamma, variant))
-    diss = (lambda a, b, N: fx.llf_dissipation(a, b, N, gamma)) if dissipation else None
+    diss = fx.surface_dissipation(dissipation, gamma)
     n, nq, E = ops.n, ops.nq, gm.E
     chi3 = kron3(ops.chi, ops.chi, ops.chi)            # Nq^3 x n^3
     Pi3 = kron3(ops.Pi, ops.Pi, ops.Pi)                # n^3 x Nq^3
@@ -440,7 +440,7 @@ class GLScheme:
         self.ops = GLOperators1D(p, c, quad, overint)
         self.mesh = GLMesh(p, ne, self.ops, lo, hi, beta, l)
         self.p, self.gamma, self.c = p, float(gamma), float(c)
-        self.variant, self.dissipation, self.mass, self.source = variant, bool(dissipation), mass, bool(source)
+        self.variant, self.dissipation, self.mass, self.source = variant, dissipation, mass, bool(source)
 
     @property
     def X(self):

@@ -96,7 +96,7 @@ def ec_two_point(gamma, variant):
 def residual(mesh, U, gamma, variant=0, dissipation=False, two_point=None):
     """Pre-mass NSFR residual R = R_vol + R_surf (line-wise form)."""
     tp = two_point or ec_two_point(gamma, variant)
-    diss = (lambda a, b, N: fx.llf_dissipation(a, b, N, gamma)) if dissipation else None
+    diss = fx.surface_dissipation(dissipation, gamma)
     return volume_residual(mesh, U, gamma, tp) + surface_residual(mesh, U, gamma, tp, diss)
 
 
@@ -168,7 +168,7 @@ def residual_definition(mesh, U, gamma, variant=0, dissipation=False, two_point=
     R = [chi_v^T chi_f^T][(Q~ - Q~^T) o F^r] 1 + sum_f chi_f^T W_f n^r . f*.
     Memory grows as E (N_v + N_fp)^2: small meshes only."""
     tp = two_point or ec_two_point(gamma, variant)
-    diss = (lambda a, b, N: fx.llf_dissipation(a, b, N, gamma)) if dissipation else None
+    diss = fx.surface_dissipation(dissipation, gamma)
     ops = mesh.ops
     n = mesh.n
     Nv = n ** 3

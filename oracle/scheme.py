@@ -23,7 +23,7 @@ class Scheme:
                  c=0.0, variant=0, dissipation=False, source=False, mass="wa"):
         self.mesh = Mesh(p, ne, lo, hi, beta, l)
         self.p, self.gamma, self.c = p, float(gamma), float(c)
-        self.variant, self.dissipation, self.source = variant, bool(dissipation), bool(source)
+        self.variant, self.dissipation, self.source = variant, dissipation, bool(source)
         self.mass = mass
 
     @property

@@ -67,7 +67,7 @@ static nsfr_status validate(const nsfr_config* c) {
     if (!(c->c_fr >= 0.0) || !std::isfinite(c->c_fr)) return bad("c_fr must be finite and >= 0");
     if (!std::isfinite(c->warp_beta)) return bad("warp_beta must be finite");
     if (c->flux < 0 || c->flux > 1) return bad("flux must be 0 or 1");
-    if (c->surface_diss < 0 || c->surface_diss > 1) return bad("surface_diss must be 0 or 1");
+    if (c->surface_diss < 0 || c->surface_diss > 2) return bad("surface_diss must be 0, 1 or 2");
     if (c->source < 0 || c->source > 1) return bad("source must be 0 or 1");
     if (c->tile < 0 || c->tile > max_epb(c->p)) return bad("tile out of range for this p");
     return NSFR_OK;

@@ -55,7 +55,7 @@ __device__ __forceinline__ void line_pass(double* lr, int epb, int dir, const do
 // after the pair sweep the primitive block is reused for the residual
 // accumulator [5][N3]. Line data are read from LDS inside the pair loop, so a
 // thread keeps only the residual of its line in registers.
-template <int P, bool CWA, int VARIANT>
+template <int P, bool CWA, int VARIANT, int DISS>
 __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0, double* lds) {
     constexpr int N = P + 1, N2 = N * N, N3 = N2 * N, LINES = 3 * N2;
     constexpr int PN3 = padded_block<N>();          // padded stride of a primitive component
@@ -148,12 +148,14 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
                          nz = sg * (Lc[2 * N3 + aown * N2] + cnz);
             double F[5];
             ec_flux<VARIANT>(qo, qn, nx, ny, nz, c1, pref, F);
-            if (A.diss) {
+            if (DISS == 1) {
                 const double* Uo = A.Uin + e * N3 + base + aown * stride;
                 double Uo5[5];
 #pragma unroll
                 for (int s = 0; s < 5; ++s) Uo5[s] = Uo[s * SE];
                 llf_add(qo, qn, Uo5, Un5, nx, ny, nz, A.gamma, pref, F);
+            } else if (DISS == 2) {
+                roe_add(qo, qn, nx, ny, nz, A.gamma, pref, F);
             }
 #pragma unroll
             for (int s = 0; s < 5; ++s) R[s][aown] += F[s];
@@ -300,11 +302,11 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
 // threads per element of the stage kernel: one per line
 __host__ __device__ constexpr int stage_threads_per_elem(int n) { return 3 * n * n; }
 
-template <int P, bool CWA, int VARIANT>
+template <int P, bool CWA, int VARIANT, int DISS>
 __global__ __launch_bounds__(STAGE_BLOCK_MAX) void stage_kernel(StageArgs A) {
     extern __shared__ double lds[];
     const int g = xcd_remap(blockIdx.x, gridDim.x);
-    stage_body<P, CWA, VARIANT>(A, (int64_t)g * A.epb, lds);
+    stage_body<P, CWA, VARIANT, DISS>(A, (int64_t)g * A.epb, lds);
 }
 
 // Persistent ensemble kernel: every workgroup walks the work list (flow,
@@ -323,7 +325,7 @@ __global__ __launch_bounds__(STAGE_BLOCK_MAX) void ensemble_kernel(const StageAr
         const StageArgs& A = table[f];
         switch (__builtin_amdgcn_readfirstlane(kinds[f])) {
 #define NSFR_CASE(P, C, V) \
-    case kind_code(P, C, V): stage_body<P, C, V>(A, e0, lds); break;
+    case kind_code(P, C, V): stage_body<P, C, V, 0>(A, e0, lds); break;
             NSFR_CASE(2, false, 0) NSFR_CASE(2, false, 1) NSFR_CASE(2, true, 0) NSFR_CASE(2, true, 1)
             NSFR_CASE(3, false, 0) NSFR_CASE(3, false, 1) NSFR_CASE(3, true, 0) NSFR_CASE(3, true, 1)
             NSFR_CASE(4, false, 0) NSFR_CASE(4, false, 1) NSFR_CASE(4, true, 0) NSFR_CASE(4, true, 1)
@@ -364,20 +366,32 @@ int default_epb(int p) {
     }
 }
 
-template <int P, bool CWA, int V>
+template <int P, bool CWA, int V, int DISS>
 static hipError_t launch_t(const StageArgs& a, hipStream_t s) {
     constexpr int N = P + 1;
     int threads = ((a.epb * stage_threads_per_elem(N) + 63) / 64) * 64;
-    size_t lds = (size_t)a.epb * stage_lds_doubles(N) * sizeof(double);
+    size_t lds = stage_lds_bytes(P, a.epb);
     unsigned blocks = (unsigned)((a.geo.E + a.epb - 1) / a.epb);
-    stage_kernel<P, CWA, V><<<blocks, threads, lds, s>>>(a);
+    stage_kernel<P, CWA, V, DISS><<<blocks, threads, lds, s>>>(a);
     return hipGetLastError();
+}
+
+// surface dissipation as a template parameter: the kernels without it keep
+// the register budget of the pure entropy-conserving flux
+template <int P, bool CWA, int V>
+static hipError_t launch_d(const StageArgs& a, hipStream_t s) {
+    switch (a.diss) {
+        case 0: return launch_t<P, CWA, V, 0>(a, s);
+        case 1: return launch_t<P, CWA, V, 1>(a, s);
+        case 2: return launch_t<P, CWA, V, 2>(a, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 template <int P>
 static hipError_t launch_p(bool cwa, int v, const StageArgs& a, hipStream_t s) {
-    if (cwa) return v ? launch_t<P, true, 1>(a, s) : launch_t<P, true, 0>(a, s);
-    return v ? launch_t<P, false, 1>(a, s) : launch_t<P, false, 0>(a, s);
+    if (cwa) return v ? launch_d<P, true, 1>(a, s) : launch_d<P, true, 0>(a, s);
+    return v ? launch_d<P, false, 1>(a, s) : launch_d<P, false, 0>(a, s);
 }
 
 hipError_t launch_stage(int p, bool cwa, int variant, const StageArgs& a, hipStream_t s) {

@@ -19,7 +19,7 @@ def make_pair(p, ne, beta=0.2, c=0.0, flux=0, diss=0, source=0, lo=0.0, hi=TWO_P
     if isinstance(ne, int):
         ne = (ne, ne, ne)
     g = NSFR(p, ne, lo=lo, hi=hi, beta=beta, gamma=G, c=c, flux=flux, diss=diss, source=source, tile=tile)
-    o = oracle.Scheme(p, ne, lo=lo, hi=hi, beta=beta, gamma=G, c=c, variant=flux, dissipation=bool(diss),
+    o = oracle.Scheme(p, ne, lo=lo, hi=hi, beta=beta, gamma=G, c=c, variant=flux, dissipation=int(diss),
                       source=bool(source))
     return g, o
 
@@ -30,7 +30,7 @@ def make_ext(p, ne, beta=0.2, c=0.0, flux=0, diss=0, source=0, lo=0.0, hi=TWO_PI
     code in plain FP64), optionally at sampled elements only."""
     if isinstance(ne, int):
         ne = (ne, ne, ne)
-    return extended.SchemeX(p, ne, lo=lo, hi=hi, beta=beta, gamma=G, c=c, variant=flux, dissipation=bool(diss),
+    return extended.SchemeX(p, ne, lo=lo, hi=hi, beta=beta, gamma=G, c=c, variant=flux, dissipation=int(diss),
                             source=bool(source), dt=dt, elements=elements)
 
 

@@ -82,8 +82,11 @@ def test_single_element_periodic(p, lib):
 
 
 @pytest.mark.parametrize("p", [2, 4])
-def test_mms_source_and_dissipation(p, lib):
-    kw = dict(beta=0.02, lo=-1.0, hi=1.0, diss=1, source=1, c=oracle.operators.c_hu(p))
+@pytest.mark.parametrize("diss", [1, 2])
+def test_mms_source_and_dissipation(p, diss, lib):
+    """Manufactured state with its source and a dissipative surface flux (1:
+    local Lax-Friedrichs, 2: entropy-stable Roe-type matrix dissipation)."""
+    kw = dict(beta=0.02, lo=-1.0, hi=1.0, diss=diss, source=1, c=oracle.operators.c_hu(p))
     g, o = make_pair(p, (3, 2, 2), **kw)
     xs = make_ext(p, (3, 2, 2), **kw)
     x64 = make_ext(p, (3, 2, 2), dt=np.float64, **kw)
@@ -92,6 +95,19 @@ def test_mms_source_and_dissipation(p, lib):
     Un = U.numpy()
     assert_ext(g.residual(cuda(U), t=t), xs.residual(Un, t), [o.residual(U, t), x64.residual(Un, t)], "mms residual")
     assert_ext(g.rhs(cuda(U), t=t), xs.rhs(Un, t), [o.rhs(U, t), x64.rhs(Un, t)], "mms rhs")
+
+
+@pytest.mark.parametrize("p", [2, 3, 5])
+def test_roe_dissipation_rough_state(p, lib):
+    """Large face jumps (seeded rough state) through the Roe-type dissipation,
+    c = c_HU, both flux variants."""
+    for flux in (0, 1):
+        kw = dict(beta=0.2, diss=2, flux=flux, c=oracle.operators.c_hu(p))
+        g, o = make_pair(p, (3, 2, 2), **kw)
+        U = state(o, "rough", seed=40 + p)
+        Un = U.numpy()
+        assert_ext(g.rhs(cuda(U)), make_ext(p, (3, 2, 2), **kw).rhs(Un),
+                   [o.rhs(U), make_ext(p, (3, 2, 2), dt=np.float64, **kw).rhs(Un)], f"roe p={p} flux={flux}")
 
 
 @pytest.mark.parametrize("p", [3, 4, 5])

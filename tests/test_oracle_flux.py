@@ -159,3 +159,58 @@ def test_llf_dissipation_is_entropy_dissipative():
     d = fx.llf_dissipation(Ua, Ub, N, G)
     dv = fx.entropy_variables(Ub, G) - fx.entropy_variables(Ua, G)
     assert float((dv * d).sum(0).max()) <= 0.0
+
+
+# ---- entropy-stable Roe-type matrix dissipation (Sec. 6.3, Sec. 7.1)
+
+def _flux_jacobian_abs(U, n):
+    """|A| = V |Lambda| V^-1 of the physical flux Jacobian A = d(f . n)/du at one
+    state, by automatic differentiation of the physical flux and an
+    eigendecomposition (independent of the dissipation's formulas)."""
+    def fn(u):
+        f = fx.physical_flux(u[:, None], G)[:, :, 0]
+        return n[0] * f[0] + n[1] * f[1] + n[2] * f[2]
+    A = torch.autograd.functional.jacobian(fn, U)
+    lam, V = torch.linalg.eig(A)
+    return (V @ torch.diag(lam.real.abs().to(V.dtype)) @ torch.linalg.inv(V)).real
+
+
+def test_roe_dissipation_is_roe_to_first_order():
+    """For a small jump du the term is -|N| |A| du / 2 to first order: R |Lambda|
+    T R^T times dv = (du/dv)^-1 du reproduces |A| only if R and Lambda are the
+    eigenpairs of the flux Jacobian and R T R^T = du/dv (Barth's scaling)."""
+    g = torch.Generator().manual_seed(21)
+    U = rand_states(6, 22)
+    for j in range(6):
+        u0 = U[:, j].clone()
+        N = [float(torch.randn(1, generator=g, dtype=torch.float64)) for _ in range(3)]
+        nn = math.sqrt(sum(x * x for x in N))
+        du = torch.randn(5, generator=g, dtype=torch.float64)
+        eps = 1e-7
+        d = fx.roe_dissipation(u0[:, None], (u0 + eps * du)[:, None], [torch.tensor([x]) for x in N], G)[:, 0] / eps
+        ref = -0.5 * nn * _flux_jacobian_abs(u0, [x / nn for x in N]) @ du
+        assert float((d - ref).abs().max()) < 1e-5 * float(ref.abs().max()), (d, ref)
+
+
+def test_roe_dissipation_is_entropy_dissipative_and_antisymmetric():
+    Ua, Ub = rand_states(800, 23), rand_states(800, 24)
+    g = torch.Generator().manual_seed(25)
+    N = [torch.randn(800, generator=g, dtype=torch.float64) for _ in range(3)]
+    d = fx.roe_dissipation(Ua, Ub, N, G)
+    dv = fx.entropy_variables(Ub, G) - fx.entropy_variables(Ua, G)
+    assert float((dv * d).sum(0).max()) <= 0.0
+    d2 = fx.roe_dissipation(Ub, Ua, [-x for x in N], G)
+    assert float((d + d2).abs().max()) < 1e-13 * float(d.abs().max())
+    assert float(fx.roe_dissipation(Ua, Ua, N, G).abs().max()) == 0.0
+
+
+def test_roe_dissipation_two_codings_agree():
+    """The extended module's numpy coding, run in FP64, against this one."""
+    import numpy as np
+    from oracle import extended as X
+    Ua, Ub = rand_states(400, 26), rand_states(400, 27)
+    g = torch.Generator().manual_seed(28)
+    N = [torch.randn(400, generator=g, dtype=torch.float64) for _ in range(3)]
+    d = fx.roe_dissipation(Ua, Ub, N, G).numpy()
+    x = X.roe(Ua.numpy(), Ub.numpy(), [t.numpy() for t in N], np.float64(G))
+    assert np.max(np.abs(d - x)) < 1e-13 * np.max(np.abs(d))

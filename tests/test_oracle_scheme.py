@@ -233,3 +233,40 @@ def test_mms_order_of_accuracy():
         errs.append(float(err[0]))
     rate = math.log2(errs[0] / errs[1])
     assert rate > p + 0.8, (errs, rate)
+
+
+@pytest.mark.parametrize("kind", ["llf", "roe"])
+def test_dissipative_surface_conserves_and_dissipates_entropy(kind):
+    """With a dissipative surface term the scheme still conserves (Sec. 6.2) and
+    the entropy rate -v^T R (the rate of sum W J U(u) with c = 0) is negative:
+    v^T R > 0 (Sec. 6.3: the Roe-type term acts on entropy-variable jumps)."""
+    m = Mesh(3, (3, 2, 2), beta=0.2)
+    U = inputs.perturbed_state(m.X, seed=31)
+    R = residual(m, U, G, 0, kind)
+    tot = oracle.diagnostics.conservation(R)
+    mag = R.abs().reshape(5, -1).sum(1)
+    assert bool((tot.abs() <= 1e-13 * mag).all())
+    e, en = oracle.diagnostics.entropy_rate(U, R, G)
+    assert e > 1e-6 * en
+
+
+def test_mms_order_of_accuracy_roe():
+    """Sec. 7.1 with the Roe-type surface dissipation: order p + 1 (p = 2,
+    c = c_HU, 4^3 -> 8^3 elements, t_f = 1, as the LLF case above)."""
+    p, tf = 2, 1.0
+    c = oracle.operators.c_hu(p)
+    errs = []
+    for ne in (4, 8):
+        s = oracle.Scheme(p, (ne, ne, ne), lo=-1.0, hi=1.0, beta=0.002, c=c, dissipation="roe", source=True)
+        U = inputs.mms_initial_state(s.X, G)
+        dx = 2.0 / (ne * (p + 1))
+        nsteps = int(math.ceil(tf / (0.3 * dx / 3.0)))
+        dt = tf / nsteps
+        t = 0.0
+        for _ in range(nsteps):
+            U = s.rk4_step(U, dt, t)
+            t += dt
+        err = oracle.problems.l2_error(s.mesh, U, oracle.problems.mms_state(s.X, tf, G))
+        errs.append(float(err[0]))
+    rate = math.log2(errs[0] / errs[1])
+    assert rate > p + 0.8, (errs, rate)
