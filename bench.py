@@ -101,8 +101,8 @@ def per_launch(fn, reps, stream):
     return [ev[i].elapsed_time(ev[i + 1]) / 1e3 for i in range(reps)]
 
 
-def rhs_stats(nsfr, inputs, p, ne, c, reps=200, warm=20):
-    g = nsfr.NSFR(p, ne, beta=0.2, c=c)
+def rhs_stats(nsfr, inputs, p, ne, c, reps=200, warm=20, quad="lgl", overint=0):
+    g = nsfr.NSFR(p, ne, beta=0.2, c=c, quad=quad, overint=overint)
     U = inputs.tgv_state(g.node_coords().cpu()).cuda().contiguous()
     out = g.empty()
     st = torch.cuda.current_stream()
@@ -293,6 +293,16 @@ def main():
         gg, UU, r = rhs_stats(nsfr, inputs, 3, 16, 0.0)
         extra["rhs_16cubed"]["p3_c0"] = r
         del gg, UU
+        # uncollocated: Gauss-Legendre rule with q = p + 1 + overint points
+        # (entropy projection kernel + hybridised stage kernel per rhs)
+        extra["rhs_16cubed_gl"] = {}
+        for pp, ov in ((3, 0), (3, 1), (4, 0), (5, 0), (5, 3)):
+            gg, UU, r = rhs_stats(nsfr, inputs, pp, 16, nsfr.c_hu(pp), reps=100, warm=10, quad="gl", overint=ov)
+            del r["frac_hbm_roof"]
+            r["q"] = pp + 1 + ov
+            r["vs_lgl_same_p"] = r["rhs_median_us"] / extra["rhs_16cubed"][f"p{pp}"]["rhs_median_us"]
+            extra["rhs_16cubed_gl"][f"p{pp}_q{pp + 1 + ov}"] = r
+            del gg, UU
         extra["rhs_32cubed"] = {}   # working sets of 0.3-1.1 GB: beyond the 256 MB last-level cache
         for pp in (3, 4, 5):
             gg, UU, r = rhs_stats(nsfr, inputs, pp, 32, nsfr.c_hu(pp), reps=200, warm=10)

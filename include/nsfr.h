@@ -74,17 +74,33 @@ typedef struct {
     int32_t source;       /* 0: none; 1: manufactured-solution source of Sec. 7.1        */
     int32_t tile;         /* elements per workgroup of the stage kernel, 3 (p+1)^2 threads
                              (one per line) each, within 512 threads and 64 KB of LDS
-                             (p = 2..5: at most 17, 7, 4, 2); 0 = tuned default          */
+                             (p = 2..5: at most 17, 7, 4, 2); 0 = tuned default. Must be
+                             0 with quad = 1                                            */
+    int32_t quad;         /* volume and surface quadrature (Sec. 3.3, Sec. 7 opening
+                             paragraph): 0 = the LGL nodes themselves (collocated NSFR);
+                             1 = Gauss-Legendre with p + 1 + overint points per direction,
+                             the solution still stored as values at the LGL nodes, with the
+                             entropy projection u~ = u(chi Pi v(chi u)) feeding the
+                             two-point fluxes of the hybridised operator                 */
+    int32_t overint;      /* extra quadrature points per direction (overintegration),
+                             0..3; must be 0 with quad = 0                               */
 } nsfr_config;
 
 typedef struct nsfr_ctx nsfr_ctx;
 
 /* Create a context on the current HIP device: builds the 1D LGL operators on
  * the host, the warped mesh, conservative-curl metric terms (Sec. 2.2, Eq. GCL)
- * and 1/(W J) on the device, and allocates the workspace. hip_stream may be
- * NULL (default stream). Errors: NSFR_EINVAL (p outside 2..5, ne < 1, hi <= lo,
- * gamma <= 1, flux/surface_diss/source out of range, negative tile),
- * NSFR_ENOMEM, NSFR_EHIP, NSFR_EUNPHYSICAL if some node has J <= 0. */
+ * and 1/(W J) on the device, and allocates the workspace. With quad = 1 it
+ * also builds the Gauss-Legendre operators (basis at the points, L2 and ESFR
+ * projections, flux-basis operator and end values) and evaluates the
+ * cofactors, x and 1/(W J) at the volume points and the cofactors at the face
+ * points (the LGL-grid polynomials, so the discrete GCL holds there too).
+ * hip_stream may be NULL (default stream). Errors: NSFR_EINVAL (p outside
+ * 2..5, ne < 1, hi <= lo, gamma <= 1, flux/surface_diss/source/quad/overint
+ * out of range, negative tile, tile with quad = 1, overint with quad = 0),
+ * NSFR_ENOTSUP if the Gauss-Legendre kernels need more LDS per workgroup than
+ * the device allows, NSFR_ENOMEM, NSFR_EHIP, NSFR_EUNPHYSICAL if some node or
+ * quadrature point has J <= 0. */
 nsfr_status nsfr_create(const nsfr_config* cfg, void* hip_stream, nsfr_ctx** out);
 nsfr_status nsfr_destroy(nsfr_ctx* ctx);
 nsfr_status nsfr_set_stream(nsfr_ctx* ctx, void* hip_stream);
@@ -150,7 +166,9 @@ nsfr_status nsfr_cfl_dt(nsfr_ctx* ctx, const double* U, double cfl, double* dt_d
 /* Vector-Jacobian product g = (d(dU/dt)/dU)^T lam of nsfr_rhs at (U, t),
  * including the Jacobians of the two-point volume and surface fluxes. The
  * weight-adjusted inverse is symmetric, so g = -(dR/dU)^T (A lam). g may not
- * alias U or lam. */
+ * alias U or lam. Collocated scheme with the EC surface flux only
+ * (quad = 0, surface_diss = 0), else NSFR_ENOTSUP; the same for
+ * nsfr_rk4_step_vjp. */
 nsfr_status nsfr_rhs_vjp(nsfr_ctx* ctx, const double* U, const double* lam, double* g, double t);
 
 /* Discrete adjoint of one RK4 step: given U^n, the step size and
@@ -161,13 +179,16 @@ nsfr_status nsfr_rk4_step_vjp(nsfr_ctx* ctx, const double* U, const double* dt_d
 
 /* Diagnostics of R(U, t) (Sec. 6.2, 6.3, 7.3) into device array out (8 doubles):
  * [sum v.R, sum |v.R|, sum R_rho, sum R_mx, sum R_my, sum R_mz, sum R_E, max |R|],
- * v the entropy variables. Uses the library workspace. */
+ * v the entropy variables at the nodes (quad = 0) or the projected entropy
+ * variables v^ = Pi v(chi u) (quad = 1, the variables whose product with R
+ * vanishes, Sec. 6.3). Uses the library workspace. */
 nsfr_status nsfr_diagnostics(nsfr_ctx* ctx, const double* U, double t, double* out);
 
 /* Kinetic energy J_KE = sum over nodes of W J rho |u|^2 / 2 into ke_dev[0]
  * (device), and, if grad is not NULL, its gradient dJ_KE/dU (state-sized
  * device array): W J [-|u|^2/2, u, v, w, 0]. The objective of the
- * time-integrated sensitivity. */
+ * time-integrated sensitivity. Collocated scheme only (quad = 0, else
+ * NSFR_ENOTSUP). */
 nsfr_status nsfr_kinetic_energy(nsfr_ctx* ctx, const double* U, double* ke_dev, double* grad);
 
 /* Synchronising state check: *bad_host = number of nodes with rho <= 0,
@@ -177,8 +198,8 @@ nsfr_status nsfr_check_state(nsfr_ctx* ctx, const double* U, int32_t* bad_host);
 /* ---- ensembles of independent flows, one launch per RK stage ------------ */
 typedef struct nsfr_ens nsfr_ens;
 
-/* n_flows configurations (any mix of p, ne, c and flux; surface_diss and
- * source must be 0, else NSFR_ENOTSUP). The packed state is the
+/* n_flows configurations (any mix of p, ne, c and flux; surface_diss,
+ * source and quad must be 0, else NSFR_ENOTSUP). The packed state is the
  * concatenation of the flows' state arrays; offsets (in doubles) are
  * returned by nsfr_ens_offsets (n_flows + 1 entries, host). */
 nsfr_status nsfr_ens_create(const nsfr_config* cfgs, int32_t n_flows, void* hip_stream, nsfr_ens** out);

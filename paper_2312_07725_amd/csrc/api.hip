@@ -36,6 +36,15 @@ struct nsfr_ctx {
     int nred = 0;
     int32_t* cnt = nullptr;    // check_state counters (64)
     int epb = 0;
+    // Gauss-Legendre variant (cfg.quad = 1): q points per direction
+    int q = 0;
+    GLOps* glops = nullptr;    // device copy of the 1D operators
+    double* Cq = nullptr;      // [3][3][E][q^3] cofactors at the volume points, line-major
+    double* Cf = nullptr;      // [6][3][E][q^2] cofactor column at the face points
+    double* invWJq = nullptr;  // [E][q^3]
+    double* Xq = nullptr;      // [3][E][q^3]
+    double* vhat = nullptr;    // [5][E][n^3] projected entropy variables of the last stage's input
+    double* ft = nullptr;      // [6][5][E][q^2] their face values
     // graph cache for nsfr_rk4_run
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
@@ -70,6 +79,10 @@ static nsfr_status validate(const nsfr_config* c) {
     if (c->surface_diss < 0 || c->surface_diss > 2) return bad("surface_diss must be 0, 1 or 2");
     if (c->source < 0 || c->source > 1) return bad("source must be 0 or 1");
     if (c->tile < 0 || c->tile > max_epb(c->p)) return bad("tile out of range for this p");
+    if (c->quad < 0 || c->quad > 1) return bad("quad must be 0 (LGL collocated) or 1 (Gauss-Legendre)");
+    if (c->overint < 0 || c->overint > MAX_OVERINT) return bad("overint must be in 0..3");
+    if (c->quad == 0 && c->overint != 0) return bad("overintegration needs the Gauss-Legendre rule (quad = 1)");
+    if (c->quad == 1 && c->tile != 0) return bad("the Gauss-Legendre kernels take no tile (tile must be 0)");
     return NSFR_OK;
 }
 
@@ -86,11 +99,13 @@ static void free_ctx(nsfr_ctx* c) {
     if (!c) return;
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
-    double* bufs[] = {c->X, c->Cline, c->invWJ, c->J, c->wsR, c->wsR2, c->red};
+    double* bufs[] = {c->X, c->Cline, c->invWJ, c->J, c->wsR, c->wsR2, c->red,
+                      c->Cq, c->Cf, c->invWJq, c->Xq, c->vhat, c->ft};
     for (double* b : bufs)
         if (b) (void)hipFree(b);
     if (c->cnt) (void)hipFree(c->cnt);
     if (c->nbr) (void)hipFree(c->nbr);
+    if (c->glops) (void)hipFree(c->glops);
     delete c;
 }
 
@@ -114,8 +129,21 @@ static StageArgs base_args(const nsfr_ctx* c) {
     return a;
 }
 
+static GLArgs gl_args(const nsfr_ctx* c) {
+    GLArgs g;
+    g.ops = c->glops;
+    g.geo.Cq = c->Cq;
+    g.geo.Cf = c->Cf;
+    g.geo.invWJ = c->invWJq;
+    g.geo.Xq = c->Xq;
+    g.vhat = c->vhat;
+    g.ft = c->ft;
+    return g;
+}
+
 static nsfr_status stage(nsfr_ctx* c, StageArgs& a) {
-    hipError_t e = launch_stage(c->p, c->cfg.c_fr != 0.0, c->cfg.flux, a, c->stream);
+    hipError_t e = c->cfg.quad ? launch_gl_stage(c->p, c->q, c->cfg.flux, a, gl_args(c), c->stream)
+                               : launch_stage(c->p, c->cfg.c_fr != 0.0, c->cfg.flux, a, c->stream);
     if (e != hipSuccess) {
         set_error(std::string("stage kernel launch: ") + hipGetErrorString(e));
         return NSFR_EHIP;
@@ -163,6 +191,49 @@ const char* nsfr_status_string(nsfr_status s) {
 }
 
 const char* nsfr_last_error(void) { return g_last_error.c_str(); }
+
+// Gauss-Legendre operators, metric terms at the quadrature points and the
+// projection buffers (the context's LGL geometry is already built).
+static nsfr_status gl_setup(nsfr_ctx* c) {
+    const int q = c->n + c->cfg.overint;
+    c->q = q;
+    const size_t need = gl_lds_bytes(c->p, q);
+    int lds_max = 0;
+    HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, c->dev));
+    if (need > (size_t)lds_max) {
+        set_error("Gauss-Legendre kernels for p = " + std::to_string(c->p) + ", " + std::to_string(q) +
+                  " points need " + std::to_string(need) + " bytes of LDS per workgroup; the device allows " +
+                  std::to_string(lds_max));
+        return NSFR_ENOTSUP;
+    }
+    HIP_TRY(gl_prepare(c->p, q));
+    GLOps h;
+    build_gl_ops(c->p, q, c->cfg.c_fr, c->hops, h);
+    const size_t E = (size_t)c->E, q2 = (size_t)q * q, q3 = q2 * q;
+    struct A { double** p; size_t n; } allocs[] = {
+        {&c->Cq, 9 * E * q3}, {&c->Cf, 18 * E * q2}, {&c->invWJq, E * q3}, {&c->Xq, 3 * E * q3},
+        {&c->vhat, 5 * E * c->n3}, {&c->ft, 30 * E * q2}};
+    for (auto& al : allocs)
+        if (hipMalloc((void**)al.p, al.n * sizeof(double)) != hipSuccess) {
+            set_error("hipMalloc failed for the Gauss-Legendre arrays");
+            return NSFR_ENOMEM;
+        }
+    if (hipMalloc((void**)&c->glops, sizeof(GLOps)) != hipSuccess) {
+        set_error("hipMalloc failed for the Gauss-Legendre operators");
+        return NSFR_ENOMEM;
+    }
+    HIP_TRY(hipMemcpy(c->glops, &h, sizeof(GLOps), hipMemcpyHostToDevice));
+    HIP_TRY(launch_gl_geometry(c->p, q, c->glops, c->E, c->X, c->Cline, c->Cq, c->Cf, c->invWJq, c->Xq, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    std::vector<double> iw(E * q3);
+    HIP_TRY(hipMemcpy(iw.data(), c->invWJq, iw.size() * sizeof(double), hipMemcpyDeviceToHost));
+    for (double v : iw)
+        if (!(v > 0.0)) {
+            set_error("the warped mesh has a quadrature point with J <= 0");
+            return NSFR_EUNPHYSICAL;
+        }
+    return NSFR_OK;
+}
 
 nsfr_status nsfr_create(const nsfr_config* cfg, void* hip_stream, nsfr_ctx** out) {
     if (!out) return bad("null output pointer");
@@ -248,6 +319,13 @@ nsfr_status nsfr_create(const nsfr_config* cfg, void* hip_stream, nsfr_ctx** out
             free_ctx(c);
             return NSFR_EUNPHYSICAL;
         }
+    if (cfg->quad) {
+        st = gl_setup(c);
+        if (st != NSFR_OK) {
+            free_ctx(c);
+            return st;
+        }
+    }
     *out = c;
     return NSFR_OK;
 }
@@ -411,13 +489,20 @@ nsfr_status nsfr_diagnostics(nsfr_ctx* c, const double* U, double t, double* out
     if (!c || !aligned(U) || !aligned(out)) return bad("null or misaligned argument");
     nsfr_status st = nsfr_residual(c, U, c->wsR, t);
     if (st) return st;
-    HIP_TRY(launch_diagnostics((int64_t)c->E * c->n3, U, c->wsR, c->cfg.gamma, c->red, c->nred, out, c->stream));
+    // Gauss-Legendre: the entropy rate pairs R with the projected entropy
+    // variables that the residual evaluation left in vhat
+    HIP_TRY(launch_diagnostics((int64_t)c->E * c->n3, U, c->cfg.quad ? c->vhat : nullptr, c->wsR, c->cfg.gamma,
+                               c->red, c->nred, out, c->stream));
     return NSFR_OK;
 }
 
 nsfr_status nsfr_kinetic_energy(nsfr_ctx* c, const double* U, double* ke, double* grad) {
     if (!c || !aligned(U) || !aligned(ke) || (grad && !aligned(grad)) || (const double*)grad == U)
         return bad("null, misaligned or aliased argument");
+    if (c->cfg.quad) {
+        set_error("kinetic_energy is built for the collocated LGL scheme (quad = 0)");
+        return NSFR_ENOTSUP;
+    }
     nsfr_status st = use_device(c);
     if (st) return st;
     HIP_TRY(launch_kinetic_energy((int64_t)c->E * c->n3, U, c->invWJ, c->red, c->nred, ke, grad, c->stream));
@@ -446,8 +531,9 @@ nsfr_status nsfr_rhs_vjp(nsfr_ctx* c, const double* U, const double* lam, double
     (void)t;   // the source term does not depend on U
     if (!c || !aligned(U) || !aligned(lam) || !aligned(g) || g == U || g == lam)
         return bad("null, misaligned or aliased argument");
-    if (c->cfg.surface_diss) {
-        set_error("rhs_vjp supports the entropy-conserving surface flux only (surface_diss = 0)");
+    if (c->cfg.surface_diss || c->cfg.quad) {
+        set_error("rhs_vjp supports the collocated scheme with the entropy-conserving surface flux only "
+                  "(surface_diss = 0, quad = 0)");
         return NSFR_ENOTSUP;
     }
     nsfr_status st = use_device(c);
@@ -466,8 +552,9 @@ nsfr_status nsfr_rk4_step_vjp(nsfr_ctx* c, const double* U, const double* dt, do
                               double* lam, double* work) {
     if (!c || !aligned(U) || !aligned(dt) || !aligned(lam_next) || !aligned(lam) || !aligned(work) || lam == U)
         return bad("null, misaligned or aliased argument");
-    if (c->cfg.surface_diss) {
-        set_error("rk4_step_vjp supports the entropy-conserving surface flux only (surface_diss = 0)");
+    if (c->cfg.surface_diss || c->cfg.quad) {
+        set_error("rk4_step_vjp supports the collocated scheme with the entropy-conserving surface flux only "
+                  "(surface_diss = 0, quad = 0)");
         return NSFR_ENOTSUP;
     }
     nsfr_status st = use_device(c);

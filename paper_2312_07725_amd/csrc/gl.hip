@@ -1,0 +1,608 @@
+// NSFR on Gauss-Legendre (uncollocated) quadrature, with overintegration:
+// metric terms at the quadrature points, the entropy projection, and the
+// fused right-hand-side / RK-stage kernel.
+//
+// Paper: Sec. 3.3 (Eq. NSFR with the hybridised operator of Eq. skew-symm
+// qtilde oper: the volume-volume block Wq Dq - Dq^T Wq per direction and the
+// surface-volume blocks phi_f^T W_f n_f; the two-point fluxes take the
+// entropy-projected conservative variables u~ = u(chi v^), v^ = Pi v(chi u^)),
+// Sec. 4 (Eq. weight-adj ESFR mass and Eq. Fr projection with the solution
+// basis evaluated at the quadrature points), Sec. 5 (sum factorisation,
+// Eq. sum-factorization: every dense 1D operator is applied one direction at a
+// time), Sec. 7 (opening paragraph: Gauss-Legendre quadrature, solution
+// coefficients on the LGL nodes, overintegration = extra quadrature points).
+//
+// The solution coefficients are the nodal values on the n^3 LGL nodes; the
+// volume rule has q^3 Gauss points (q = n + overintegration) and each face q^2
+// points. Per right-hand side two kernels run:
+//   * gl_project_kernel: interpolate u to the volume points, form the entropy
+//     variables, project them onto the solution basis (v^), and evaluate v^ at
+//     the face points of every face (the neighbours read these);
+//   * gl_stage_kernel: entropy-projected states at the volume and face points,
+//     the hybrid Hadamard sum (one thread per line: the pairs along the line,
+//     the pairs of each volume point with the two face points at the line's
+//     ends, and the surface numerical flux at those ends), the transpose
+//     interpolation of the volume and face residuals to the coefficients, the
+//     weight-adjusted inverse, and the RK combination.
+#include "nsfr_host.h"
+
+namespace nsfr {
+
+constexpr int GL_BLOCK = 256;
+
+// ---- sum-factorised 1D operator in LDS: dst = M applied along axis AX of
+// src (dims S0 x S1 x S2, x fastest) for `ns` states; M is OUT x IN
+// row-major, or its transpose stored IN x OUT when TR.
+template <int S0, int S1, int S2, int AX, int OUT, bool TR>
+__device__ __forceinline__ void lds_pass(const double* __restrict__ src, double* __restrict__ dst,
+                                         const double* __restrict__ M, int ns) {
+    constexpr int IN = AX == 0 ? S0 : (AX == 1 ? S1 : S2);
+    constexpr int D0 = AX == 0 ? OUT : S0, D1 = AX == 1 ? OUT : S1, D2 = AX == 2 ? OUT : S2;
+    constexpr int SRC = S0 * S1 * S2, DST = D0 * D1 * D2;
+    constexpr int ST = AX == 0 ? 1 : (AX == 1 ? S0 : S0 * S1);
+    for (int it = threadIdx.x; it < ns * DST; it += blockDim.x) {
+        const int s = it / DST, r = it - s * DST;
+        const int i0 = r % D0, i1 = (r / D0) % D1, i2 = r / (D0 * D1);
+        const int o = AX == 0 ? i0 : (AX == 1 ? i1 : i2);
+        const double* x = src + s * SRC + (AX == 0 ? 0 : i0) + S0 * ((AX == 1 ? 0 : i1) + S1 * (AX == 2 ? 0 : i2));
+        double acc = 0.0;
+#pragma unroll
+        for (int m = 0; m < IN; ++m) acc = __builtin_fma(TR ? M[m * OUT + o] : M[o * IN + m], x[m * ST], acc);
+        dst[s * DST + r] = acc;
+    }
+}
+
+// entropy variables v(u) of Sec. 2.1 (U = -rho s / (gamma - 1))
+__device__ __forceinline__ void entropy_vars(const double u[5], double gm1, double gamma, double v[5]) {
+    const double r = u[0], ir = 1.0 / r;
+    const double a = u[1] * ir, b = u[2] * ir, c = u[3] * ir;
+    const double q2 = a * a + b * b + c * c;
+    const double p = gm1 * (u[4] - 0.5 * r * q2);
+    const double beta = 0.5 * r / p;
+    const double s = log(p) - gamma * log(r);
+    v[0] = (gamma - s) / gm1 - beta * q2;
+    v[1] = 2.0 * beta * a;
+    v[2] = 2.0 * beta * b;
+    v[3] = 2.0 * beta * c;
+    v[4] = -2.0 * beta;
+}
+
+// primitives of u(v) (the inverse entropy map): beta = -v5 / 2,
+// u = v_m / (2 beta), s = gamma - (gamma - 1)(v1 + beta |u|^2),
+// ln p = (s + gamma ln(2 beta)) / (1 - gamma), rho = 2 beta p
+__device__ __forceinline__ PrimR prims_from_entropy(const double v[5], double gm1, double gamma, double pref) {
+    PrimR q;
+    const double beta = -0.5 * v[4];
+    const double ib = 0.5 / beta;
+    q.u = v[1] * ib;
+    q.v = v[2] * ib;
+    q.w = v[3] * ib;
+    const double s = gamma - gm1 * (v[0] + beta * (q.u * q.u + q.v * q.v + q.w * q.w));
+    const double p = exp((s + gamma * log(2.0 * beta)) / (-gm1));
+    q.rho = 2.0 * beta * p;
+    q.pd = p - pref;
+    q.beta = beta;
+    return q;
+}
+
+// ---- metric terms at the quadrature points (once per context). The
+// cofactors are the conservative-curl cofactors of the LGL grid (degree p)
+// evaluated as polynomials, J the determinant of the grid polynomial's
+// derivative; one thread per (element, volume point) and per (element,
+// face point). Cline is the line-major cofactor array of the collocated
+// geometry: column d, component m of node (a, b, c) at
+// [((d * 3 + m) * E + e) * n^3 + pos_d * n^2 + line_d] with pos = (a, b, c)
+// and line = (b + n c, a + n c, a + n b).
+template <int N>
+__device__ __forceinline__ int64_t cline_index(int d, int m, int64_t E, int64_t e, int a, int b, int c) {
+    constexpr int N2 = N * N;
+    const int pos = d == 0 ? a : (d == 1 ? b : c);
+    const int lin = d == 0 ? b + N * c : (d == 1 ? a + N * c : a + N * b);
+    return ((int64_t)(d * 3 + m) * E + e) * (N2 * N) + pos * N2 + lin;
+}
+
+template <int N, int Q>
+__global__ void gl_geometry_kernel(const GLOps* __restrict__ ops, int64_t E, const double* __restrict__ X,
+                                   const double* __restrict__ Cline, double* Cq, double* invWJ, double* Xq) {
+    constexpr int N3 = N * N * N, Q2 = Q * Q, Q3 = Q2 * Q;
+    const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (gid >= E * Q3) return;
+    const int64_t e = gid / Q3;
+    const int t = (int)(gid - e * Q3);
+    const int i = t % Q, j = (t / Q) % Q, k = t / Q2;
+    const double* chi = ops->chi;
+    const double* chid = ops->chid;
+    double x[3] = {0.0, 0.0, 0.0}, G[3][3] = {}, Cv[3][3] = {};
+    for (int c = 0; c < N; ++c)
+        for (int b = 0; b < N; ++b)
+            for (int a = 0; a < N; ++a) {
+                const int nd = a + N * (b + N * c);
+                const double wi = chi[i * N + a], wj = chi[j * N + b], wk = chi[k * N + c];
+                const double w = wi * wj * wk;
+                const double w0 = chid[i * N + a] * wj * wk, w1 = wi * chid[j * N + b] * wk,
+                             w2 = wi * wj * chid[k * N + c];
+                for (int m = 0; m < 3; ++m) {
+                    const double xv = X[(m * E + e) * N3 + nd];
+                    x[m] += w * xv;
+                    G[m][0] += w0 * xv;
+                    G[m][1] += w1 * xv;
+                    G[m][2] += w2 * xv;
+                    for (int d = 0; d < 3; ++d) Cv[m][d] += w * Cline[cline_index<N>(d, m, E, e, a, b, c)];
+                }
+            }
+    const double J = G[0][0] * (G[1][1] * G[2][2] - G[1][2] * G[2][1]) -
+                     G[0][1] * (G[1][0] * G[2][2] - G[1][2] * G[2][0]) +
+                     G[0][2] * (G[1][0] * G[2][1] - G[1][1] * G[2][0]);
+    invWJ[e * Q3 + t] = 1.0 / (ops->wq[i] * ops->wq[j] * ops->wq[k] * J);
+    for (int m = 0; m < 3; ++m) Xq[(m * E + e) * Q3 + t] = x[m];
+    const int pos[3] = {i, j, k};
+    const int lin[3] = {j + Q * k, i + Q * k, i + Q * j};
+    for (int d = 0; d < 3; ++d)
+        for (int m = 0; m < 3; ++m) Cq[((int64_t)(d * 3 + m) * E + e) * Q3 + pos[d] * Q2 + lin[d]] = Cv[m][d];
+}
+
+template <int N, int Q>
+__global__ void gl_face_geometry_kernel(const GLOps* __restrict__ ops, int64_t E, const double* __restrict__ Cline,
+                                        double* Cf) {
+    constexpr int Q2 = Q * Q;
+    const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (gid >= E * 6 * Q2) return;
+    const int64_t e = gid / (6 * Q2);
+    const int r = (int)(gid - e * 6 * Q2);
+    const int f = r / Q2, t = r - f * Q2;
+    const int d = f / 2, side = f % 2;
+    const int t1 = t % Q, t2 = t / Q;
+    const int end = side ? N - 1 : 0;
+    const double* chi = ops->chi;
+    for (int m = 0; m < 3; ++m) {
+        double acc = 0.0;
+        for (int c = 0; c < N; ++c)
+            for (int b = 0; b < N; ++b) {
+                // tangential LGL indices (b, c) in increasing direction order
+                const int64_t ix = d == 0 ? cline_index<N>(d, m, E, e, end, b, c)
+                                          : (d == 1 ? cline_index<N>(d, m, E, e, b, end, c)
+                                                    : cline_index<N>(d, m, E, e, b, c, end));
+                acc += chi[t1 * N + b] * chi[t2 * N + c] * Cline[ix];
+            }
+        Cf[((int64_t)(f * 3 + m) * E + e) * Q2 + t] = acc;
+    }
+}
+
+// ---- entropy projection: v^ = Pi v(chi u^) and v^ at every face point
+template <int N, int Q>
+__global__ __launch_bounds__(GL_BLOCK) void gl_project_kernel(const GLOps* __restrict__ ops, int64_t E,
+                                                              const double* __restrict__ U, double gamma,
+                                                              double* vhat, double* ft) {
+    constexpr int N2 = N * N, N3 = N2 * N, Q2 = Q * Q, Q3 = Q2 * Q;
+    extern __shared__ double lds[];
+    double* mchi = lds;              // Q x N
+    double* mpi = mchi + Q * N;      // N x Q
+    double* A = mpi + N * Q;         // 5 Q^3
+    double* B = A + 5 * Q3;          // 5 Q^3
+    const int tid = threadIdx.x;
+    const int64_t e = blockIdx.x;
+    const int64_t SE = E * N3;
+    const double gm1 = gamma - 1.0;
+    for (int i = tid; i < Q * N; i += blockDim.x) {
+        mchi[i] = ops->chi[i];
+        mpi[i] = ops->pi[i];
+    }
+    for (int i = tid; i < 5 * N3; i += blockDim.x) {
+        const int s = i / N3, nd = i - s * N3;
+        A[i] = U[s * SE + e * N3 + nd];
+    }
+    __syncthreads();
+    lds_pass<N, N, N, 0, Q, false>(A, B, mchi, 5);
+    __syncthreads();
+    lds_pass<Q, N, N, 1, Q, false>(B, A, mchi, 5);
+    __syncthreads();
+    lds_pass<Q, Q, N, 2, Q, false>(A, B, mchi, 5);
+    __syncthreads();
+    for (int t = tid; t < Q3; t += blockDim.x) {
+        double u[5], v[5];
+#pragma unroll
+        for (int s = 0; s < 5; ++s) u[s] = B[s * Q3 + t];
+        entropy_vars(u, gm1, gamma, v);
+#pragma unroll
+        for (int s = 0; s < 5; ++s) B[s * Q3 + t] = v[s];
+    }
+    __syncthreads();
+    lds_pass<Q, Q, Q, 2, N, false>(B, A, mpi, 5);
+    __syncthreads();
+    lds_pass<Q, Q, N, 1, N, false>(A, B, mpi, 5);
+    __syncthreads();
+    lds_pass<Q, N, N, 0, N, false>(B, A, mpi, 5);
+    __syncthreads();
+    for (int i = tid; i < 5 * N3; i += blockDim.x) {
+        const int s = i / N3, nd = i - s * N3;
+        vhat[s * SE + e * N3 + nd] = A[i];
+    }
+    // v^ at the face points: the end slab of the coefficients, interpolated in
+    // the two tangential directions
+    for (int it = tid; it < 6 * 5 * Q2; it += blockDim.x) {
+        const int f = it / (5 * Q2), r = it - f * 5 * Q2;
+        const int s = r / Q2, t = r - s * Q2;
+        const int d = f / 2, end = (f % 2) ? N - 1 : 0;
+        const int t1 = t % Q, t2 = t / Q;
+        double acc = 0.0;
+#pragma unroll
+        for (int c = 0; c < N; ++c)
+#pragma unroll
+            for (int b = 0; b < N; ++b) {
+                const int nd = d == 0 ? end + N * b + N2 * c : (d == 1 ? b + N * end + N2 * c : b + N * c + N2 * end);
+                acc = __builtin_fma(mchi[t1 * N + b] * mchi[t2 * N + c], A[s * N3 + nd], acc);
+            }
+        ft[((int64_t)(f * 5 + s) * E + e) * Q2 + t] = acc;
+    }
+}
+
+// ---- the stage: one element per workgroup
+template <int N, int Q, int VARIANT>
+__global__ __launch_bounds__(GL_BLOCK) void gl_stage_kernel(StageArgs A, GLArgs G) {
+    constexpr int N2 = N * N, N3 = N2 * N, Q2 = Q * Q, Q3 = Q2 * Q;
+    extern __shared__ double lds[];
+    double* mchi = lds;               // Q x N
+    double* mpit = mchi + Q * N;      // N x Q
+    double* msq = mpit + N * Q;       // Q x Q (halved skew operator)
+    double* mtl = msq + Q2;           // Q
+    double* mtr = mtl + Q;            // Q
+    double* mw = mtr + Q;             // Q
+    double* BA = mw + Q;              // 6 Q^3: pass buffer, then the volume primitives
+    double* BB = BA + 6 * Q3;         // 5 Q^3: pass buffer, then the volume residual
+    double* FP = BB + 5 * Q3;         // [6 faces][6][Q^2]: primitives at the own face points
+    double* RF = FP + 36 * Q2;        // [6 faces][5][Q^2]: face-point residuals
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int64_t e = blockIdx.x;
+    const int64_t E = A.geo.E;
+    const int64_t SE = E * N3;
+    const double gamma = A.gamma, gm1 = gamma - 1.0, c1 = A.c1;
+    const double pref = reference_pressure(A.Uin, SE, gm1);
+    const GLOps* ops = G.ops;
+    for (int i = tid; i < Q * N; i += nth) {
+        mchi[i] = ops->chi[i];
+        mpit[i] = ops->pit[i];
+    }
+    for (int i = tid; i < Q2; i += nth) msq[i] = ops->sqh[i];
+    for (int i = tid; i < Q; i += nth) {
+        mtl[i] = ops->tl[i];
+        mtr[i] = ops->tr[i];
+        mw[i] = ops->wq[i];
+    }
+    // 1. v^ of this element -> volume points; own face points from the face traces
+    for (int i = tid; i < 5 * N3; i += nth) {
+        const int s = i / N3, nd = i - s * N3;
+        BA[i] = G.vhat[s * SE + e * N3 + nd];
+    }
+    for (int it = tid; it < 6 * Q2; it += nth) {
+        const int f = it / Q2, t = it - f * Q2;
+        double v[5];
+#pragma unroll
+        for (int s = 0; s < 5; ++s) v[s] = G.ft[((int64_t)(f * 5 + s) * E + e) * Q2 + t];
+        const PrimR q = prims_from_entropy(v, gm1, gamma, pref);
+        double* L = FP + f * 6 * Q2 + t;
+        L[0] = q.rho;
+        L[Q2] = q.u;
+        L[2 * Q2] = q.v;
+        L[3 * Q2] = q.w;
+        L[4 * Q2] = q.pd;
+        L[5 * Q2] = q.beta;
+    }
+    __syncthreads();
+    lds_pass<N, N, N, 0, Q, false>(BA, BB, mchi, 5);
+    __syncthreads();
+    lds_pass<Q, N, N, 1, Q, false>(BB, BA, mchi, 5);
+    __syncthreads();
+    lds_pass<Q, Q, N, 2, Q, false>(BA, BB, mchi, 5);
+    __syncthreads();
+    for (int t = tid; t < Q3; t += nth) {
+        double v[5];
+#pragma unroll
+        for (int s = 0; s < 5; ++s) v[s] = BB[s * Q3 + t];
+        const PrimR q = prims_from_entropy(v, gm1, gamma, pref);
+        BA[t] = q.rho;
+        BA[Q3 + t] = q.u;
+        BA[2 * Q3 + t] = q.v;
+        BA[3 * Q3 + t] = q.w;
+        BA[4 * Q3 + t] = q.pd;
+        BA[5 * Q3 + t] = q.beta;
+    }
+    __syncthreads();
+
+    // 2. one thread per line: pairs along the line, pairs with the two end face
+    //    points (weights t_L, t_R), and the surface flux at both ends
+    const int lt = tid;
+    const bool active = lt < 3 * Q2;
+    const int dir = active ? lt / Q2 : 0;
+    const int l = active ? lt - dir * Q2 : 0;
+    const int t1 = l % Q, t2 = l / Q;
+    const int base = dir == 0 ? Q * t1 + Q2 * t2 : (dir == 1 ? t1 + Q2 * t2 : t1 + Q * t2);
+    const int stride = dir == 0 ? 1 : (dir == 1 ? Q : Q2);
+    double Rv[5][Q], Rf[2][5];
+#pragma unroll
+    for (int s = 0; s < 5; ++s) {
+#pragma unroll
+        for (int a = 0; a < Q; ++a) Rv[s][a] = 0.0;
+        Rf[0][s] = Rf[1][s] = 0.0;
+    }
+    if (active) {
+        const double* Cl = G.geo.Cq + (int64_t)(3 * dir) * E * Q3 + e * Q3 + l;   // [comp][pos Q^2]
+        const int64_t CS = E * Q3;
+        auto volp = [&](int a) {
+            const int t = base + a * stride;
+            return PrimR{BA[t], BA[Q3 + t], BA[2 * Q3 + t], BA[3 * Q3 + t], BA[4 * Q3 + t], BA[5 * Q3 + t]};
+        };
+        // volume-volume pairs (S/2 folded into msq, direction C(a) + C(b))
+#pragma unroll
+        for (int a = 0; a < Q - 1; ++a) {
+            const PrimR qa = volp(a);
+            const double cax = Cl[a * Q2], cay = Cl[CS + a * Q2], caz = Cl[2 * CS + a * Q2];
+#pragma unroll
+            for (int b = a + 1; b < Q; ++b) {
+                const PrimR qb = volp(b);
+                double F[5];
+                ec_flux<VARIANT>(qa, qb, cax + Cl[b * Q2], cay + Cl[CS + b * Q2], caz + Cl[2 * CS + b * Q2], c1, pref,
+                                 F);
+                const double sab = msq[a * Q + b];
+#pragma unroll
+                for (int s = 0; s < 5; ++s) {
+                    Rv[s][a] = __builtin_fma(sab, F[s], Rv[s][a]);
+                    Rv[s][b] = __builtin_fma(-sab, F[s], Rv[s][b]);
+                }
+            }
+        }
+        // the two ends of the line
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const int f = 2 * dir + side;
+            const double sg = side ? 1.0 : -1.0;
+            const double* tw = side ? mtr : mtl;
+            const double* Fp = FP + f * 6 * Q2 + l;
+            const PrimR qf = PrimR{Fp[0], Fp[Q2], Fp[2 * Q2], Fp[3 * Q2], Fp[4 * Q2], Fp[5 * Q2]};
+            const double* Cfo = G.geo.Cf + ((int64_t)(f * 3) * E + e) * Q2 + l;
+            const int64_t FS = E * Q2;
+            const double cfx = Cfo[0], cfy = Cfo[FS], cfz = Cfo[2 * FS];
+            // volume-face pairs: +/- t[a] W_perp F(u~_a, u~_f; (C_a + C_f)/2) on the volume
+            // point, the opposite on the face point
+#pragma unroll
+            for (int a = 0; a < Q; ++a) {
+                const PrimR qa = volp(a);
+                double F[5];
+                ec_flux<VARIANT>(qa, qf, Cl[a * Q2] + cfx, Cl[CS + a * Q2] + cfy, Cl[2 * CS + a * Q2] + cfz, c1,
+                                 pref, F);
+                const double wgt = 0.5 * sg * tw[a];
+#pragma unroll
+                for (int s = 0; s < 5; ++s) {
+                    Rv[s][a] = __builtin_fma(wgt, F[s], Rv[s][a]);
+                    Rf[side][s] = __builtin_fma(-wgt, F[s], Rf[side][s]);
+                }
+            }
+            // surface numerical flux with the neighbour's face point
+            const int en = A.geo.nbr[(int64_t)f * E + e];
+            const int fn = 2 * dir + (1 - side);
+            double vn[5];
+#pragma unroll
+            for (int s = 0; s < 5; ++s) vn[s] = G.ft[((int64_t)(fn * 5 + s) * E + en) * Q2 + l];
+            const PrimR qn = prims_from_entropy(vn, gm1, gamma, pref);
+            const double* Cfn = G.geo.Cf + ((int64_t)(fn * 3) * E + en) * Q2 + l;
+            const double nx = 0.5 * sg * (cfx + Cfn[0]), ny = 0.5 * sg * (cfy + Cfn[FS]),
+                         nz = 0.5 * sg * (cfz + Cfn[2 * FS]);
+            double F[5];
+            ec_flux<VARIANT>(qf, qn, nx, ny, nz, c1, pref, F);
+            if (A.diss == 1) {
+                const double gmr = gm1;
+                auto cons = [&](const PrimR& q, double out[5]) {
+                    out[0] = q.rho;
+                    out[1] = q.rho * q.u;
+                    out[2] = q.rho * q.v;
+                    out[3] = q.rho * q.w;
+                    out[4] = (pref + q.pd) / gmr + 0.5 * q.rho * (q.u * q.u + q.v * q.v + q.w * q.w);
+                };
+                double Uo[5], Un[5];
+                cons(qf, Uo);
+                cons(qn, Un);
+                llf_add(qf, qn, Uo, Un, nx, ny, nz, gamma, pref, F);
+            } else if (A.diss == 2) {
+                roe_add(qf, qn, nx, ny, nz, gamma, pref, F);
+            }
+#pragma unroll
+            for (int s = 0; s < 5; ++s) Rf[side][s] += F[s];
+        }
+    }
+    __syncthreads();   // the volume primitives (BA) are no longer read
+    // volume residuals of the three directions into BB (fixed order), face
+    // residuals into RF (each face point belongs to one line)
+    const double wperp = mw[t1] * mw[t2];
+    for (int ph = 0; ph < 3; ++ph) {
+        if (active && dir == ph) {
+#pragma unroll
+            for (int s = 0; s < 5; ++s)
+#pragma unroll
+                for (int a = 0; a < Q; ++a) {
+                    const double v = Rv[s][a] * wperp;
+                    double* x = BB + s * Q3 + base + a * stride;
+                    if (ph == 0) *x = v;
+                    else *x += v;
+                }
+        }
+        __syncthreads();
+    }
+    if (active) {
+#pragma unroll
+        for (int side = 0; side < 2; ++side)
+#pragma unroll
+            for (int s = 0; s < 5; ++s) RF[((2 * dir + side) * 5 + s) * Q2 + l] = Rf[side][s] * wperp;
+    }
+    // manufactured source at the volume points: R -= W J q
+    const int mode = A.mode;
+    double dt = 0.0, cstage = 0.0;
+    if (mode >= MODE_RK1) {
+        dt = *A.dt;
+        cstage = (mode == MODE_RK1) ? 0.0 : (mode == MODE_RK4 ? 1.0 : 0.5);
+    }
+    if (A.source) {
+        const double t = (A.tdev ? *A.tdev : A.t) + cstage * dt;
+        const int64_t EQ = E * Q3;
+        for (int p = tid; p < Q3; p += nth) {
+            double qs[5];
+            const double* X = G.geo.Xq + e * Q3 + p;
+            mms_source(X[0], X[EQ], X[2 * EQ], t, gamma, qs);
+            const double wj = 1.0 / G.geo.invWJ[e * Q3 + p];
+#pragma unroll
+            for (int s = 0; s < 5; ++s) BB[s * Q3 + p] -= wj * qs[s];
+        }
+    }
+    __syncthreads();
+
+    // 3. to the coefficients: chi^T along z, y, x of the volume residual, then
+    //    the face residuals through the tangential chi^T onto the end slabs
+    lds_pass<Q, Q, Q, 2, N, true>(BB, BA, mchi, 5);
+    __syncthreads();
+    lds_pass<Q, Q, N, 1, N, true>(BA, BB, mchi, 5);
+    __syncthreads();
+    lds_pass<Q, N, N, 0, N, true>(BB, BA, mchi, 5);
+    __syncthreads();
+    for (int it = tid; it < 5 * N3; it += nth) {
+        const int s = it / N3, nd = it - s * N3;
+        const int a = nd % N, b = (nd / N) % N, c = nd / N2;
+        double acc = BA[it];
+        const int crd[3] = {a, b, c};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int u1 = d == 0 ? b : a, u2 = d == 2 ? b : c;   // tangential coefficient indices
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                if (crd[d] != (side ? N - 1 : 0)) continue;
+                const double* r = RF + ((2 * d + side) * 5 + s) * Q2;
+                double f = 0.0;
+                for (int q2 = 0; q2 < Q; ++q2)
+                    for (int q1 = 0; q1 < Q; ++q1) f = __builtin_fma(mchi[q1 * N + u1] * mchi[q2 * N + u2], r[q1 + Q * q2], f);
+                acc += f;
+            }
+        }
+        BA[it] = acc;
+    }
+    __syncthreads();
+    if (mode == MODE_RESIDUAL) {
+        for (int it = tid; it < 5 * N3; it += nth) {
+            const int s = it / N3, nd = it - s * N3;
+            A.out[s * SE + e * N3 + nd] = BA[it];
+        }
+        return;
+    }
+    // 4. weight-adjusted inverse: Pi~^T (coefficients -> points), (W J)^-1, Pi~
+    lds_pass<N, N, N, 0, Q, true>(BA, BB, mpit, 5);
+    __syncthreads();
+    lds_pass<Q, N, N, 1, Q, true>(BB, BA, mpit, 5);
+    __syncthreads();
+    lds_pass<Q, Q, N, 2, Q, true>(BA, BB, mpit, 5);
+    __syncthreads();
+    for (int it = tid; it < 5 * Q3; it += nth) BB[it] *= G.geo.invWJ[e * Q3 + it % Q3];
+    __syncthreads();
+    lds_pass<Q, Q, Q, 2, N, false>(BB, BA, mpit, 5);
+    __syncthreads();
+    lds_pass<Q, Q, N, 1, N, false>(BA, BB, mpit, 5);
+    __syncthreads();
+    lds_pass<Q, N, N, 0, N, false>(BB, BA, mpit, 5);
+    __syncthreads();
+    // 5. RK combination
+    for (int it = tid; it < 5 * N3; it += nth) {
+        const int s = it / N3, nd = it - s * N3;
+        const int64_t gi = s * SE + e * N3 + nd;
+        const double k = -BA[it];
+        switch (mode) {
+            case MODE_RHS: A.out[gi] = k; break;
+            case MODE_RK1: {
+                const double u = A.Uin[gi];
+                A.acc[gi] = __builtin_fma(dt / 6.0, k, u);
+                A.out[gi] = __builtin_fma(0.5 * dt, k, u);
+            } break;
+            case MODE_RK2:
+                A.acc[gi] = __builtin_fma(dt / 3.0, k, A.acc[gi]);
+                A.out[gi] = __builtin_fma(0.5 * dt, k, A.Un[gi]);
+                break;
+            case MODE_RK3:
+                A.acc[gi] = __builtin_fma(dt / 3.0, k, A.acc[gi]);
+                A.out[gi] = __builtin_fma(dt, k, A.Un[gi]);
+                break;
+            default: A.out[gi] = __builtin_fma(dt / 6.0, k, A.acc[gi]); break;
+        }
+    }
+}
+
+static size_t gl_stage_lds(int p, int q) {
+    const int n = p + 1;
+    return (size_t)(2 * q * n + q * q + 3 * q + 11 * q * q * q + 66 * q * q) * sizeof(double);
+}
+
+static size_t gl_project_lds(int p, int q) { return (size_t)(2 * q * (p + 1) + 10 * q * q * q) * sizeof(double); }
+
+size_t gl_lds_bytes(int p, int q) {
+    const size_t a = gl_stage_lds(p, q), b = gl_project_lds(p, q);
+    return a > b ? a : b;
+}
+
+template <int N, int Q>
+static hipError_t gl_geometry_nq(const GLOps* ops, int64_t E, const double* X, const double* Cline, double* Cq,
+                                 double* Cf, double* invWJ, double* Xq, hipStream_t s) {
+    const int64_t nv = E * Q * Q * Q, nf = E * 6 * Q * Q;
+    gl_geometry_kernel<N, Q><<<(unsigned)((nv + 127) / 128), 128, 0, s>>>(ops, E, X, Cline, Cq, invWJ, Xq);
+    gl_face_geometry_kernel<N, Q><<<(unsigned)((nf + 127) / 128), 128, 0, s>>>(ops, E, Cline, Cf);
+    return hipGetLastError();
+}
+
+template <int N, int Q>
+static hipError_t gl_stage_nq(int variant, const StageArgs& a, const GLArgs& g, hipStream_t s) {
+    const size_t lp = gl_project_lds(N - 1, Q), ls = gl_stage_lds(N - 1, Q);
+    const unsigned blocks = (unsigned)a.geo.E;
+    const int threads = ((3 * Q * Q + 63) / 64) * 64;
+    gl_project_kernel<N, Q><<<blocks, GL_BLOCK, lp, s>>>(g.ops, a.geo.E, a.Uin, a.gamma, g.vhat, g.ft);
+    if (variant) gl_stage_kernel<N, Q, 1><<<blocks, threads, ls, s>>>(a, g);
+    else gl_stage_kernel<N, Q, 0><<<blocks, threads, ls, s>>>(a, g);
+    return hipGetLastError();
+}
+
+// configure every kernel of an (N, Q) pair for its dynamic LDS (needed when a
+// workgroup uses more than the default 64 KB)
+template <int N, int Q>
+static hipError_t gl_set_lds() {
+    hipError_t e = hipFuncSetAttribute((const void*)gl_project_kernel<N, Q>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)gl_project_lds(N - 1, Q));
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)gl_stage_kernel<N, Q, 0>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)gl_stage_lds(N - 1, Q));
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)gl_stage_kernel<N, Q, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)gl_stage_lds(N - 1, Q));
+    return e;
+}
+
+#define NSFR_GL_TABLE(X)                                                                                     \
+    X(3, 3) X(3, 4) X(3, 5) X(3, 6) X(4, 4) X(4, 5) X(4, 6) X(4, 7) X(5, 5) X(5, 6) X(5, 7) X(5, 8) X(6, 6) \
+        X(6, 7) X(6, 8) X(6, 9)
+
+hipError_t launch_gl_geometry(int p, int q, const GLOps* ops, int64_t E, const double* X, const double* Cline,
+                              double* Cq, double* Cf, double* invWJ, double* Xq, hipStream_t s) {
+#define NSFR_GEO(NN, QQ) \
+    if (p + 1 == NN && q == QQ) return gl_geometry_nq<NN, QQ>(ops, E, X, Cline, Cq, Cf, invWJ, Xq, s);
+    NSFR_GL_TABLE(NSFR_GEO)
+#undef NSFR_GEO
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_gl_stage(int p, int q, int variant, const StageArgs& a, const GLArgs& g, hipStream_t s) {
+#define NSFR_STG(NN, QQ) \
+    if (p + 1 == NN && q == QQ) return gl_stage_nq<NN, QQ>(variant, a, g, s);
+    NSFR_GL_TABLE(NSFR_STG)
+#undef NSFR_STG
+    return hipErrorInvalidValue;
+}
+
+hipError_t gl_prepare(int p, int q) {
+#define NSFR_LDS(NN, QQ) \
+    if (p + 1 == NN && q == QQ) return gl_set_lds<NN, QQ>();
+    NSFR_GL_TABLE(NSFR_LDS)
+#undef NSFR_LDS
+    return hipErrorInvalidValue;
+}
+
+}  // namespace nsfr

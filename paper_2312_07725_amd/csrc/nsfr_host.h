@@ -20,6 +20,42 @@ struct HostOps {
 
 void build_ops(int p, double c, Ops& ops, HostOps& h);
 
+// ---- uncollocated (Gauss-Legendre) quadrature
+constexpr int MAXQ = 9;   // n + overintegration, at most 6 + 3
+constexpr int MAX_OVERINT = 3;
+
+// 1D operators of the Gauss-Legendre variant (row-major; n solution nodes on
+// LGL, q quadrature points), copied to device memory once per context.
+struct GLOps {
+    int p, n, q;
+    double xq[MAXQ], wq[MAXQ];
+    double chi[MAXQ * MAXN];    // q x n: LGL Lagrange basis at the quadrature points
+    double chid[MAXQ * MAXN];   // q x n: its derivative there
+    double pi[MAXN * MAXQ];     // n x q: L2 projection M^-1 chi^T Wq
+    double pit[MAXN * MAXQ];    // n x q: ESFR projection (M + K)^-1 chi^T Wq (Eq. Fr projection)
+    double sqh[MAXQ * MAXQ];    // q x q: (Wq Dq - Dq^T Wq) / 2, exactly antisymmetric
+    double tl[MAXQ], tr[MAXQ];  // flux basis (Lagrange on the quadrature points) at -1, +1
+};
+
+void build_gl_ops(int p, int q, double c, const HostOps& h, GLOps& g);
+
+// Metric terms at the quadrature points.
+struct GLGeo {
+    const double* Cq;     // [3 dir][3 comp][E][pos * q^2 + line]: column dir of C, line-major
+    const double* Cf;     // [3 dir][2 side][3 comp][E][q^2]: column dir of C on the faces normal to dir
+                          // (face point t1 + q t2, tangential directions in increasing order)
+    const double* invWJ;  // [E][q^3]
+    const double* Xq;     // [3][E][q^3]
+};
+
+struct GLArgs {
+    const GLOps* ops;     // device copy
+    GLGeo geo;
+    double* vhat;         // [5][E][n^3]: projected entropy variables (written by the projection kernel)
+    double* ft;           // [3 dir][2 side][5][E][q^2]: their values at the face points
+};
+
+
 // Geometry of one mesh as the kernels see it.
 struct Geo {
     int nx, ny, nz;
@@ -69,8 +105,9 @@ hipError_t launch_geometry_export(int p, int64_t E, const double* Cline, double*
 hipError_t launch_max_wavespeed(int64_t nnodes, const double* U, double gamma, double* partial, int nblk,
                                 double* lam, hipStream_t s);
 hipError_t launch_cfl_dt(const double* lam, double cfl, double dx, double* dt, hipStream_t s);
-hipError_t launch_diagnostics(int64_t nnodes, const double* U, const double* R, double gamma, double* partial,
-                              int nblk, double* out, hipStream_t s);
+// V: entropy variables to pair with R, or null to evaluate v(U) at the nodes
+hipError_t launch_diagnostics(int64_t nnodes, const double* U, const double* V, const double* R, double gamma,
+                              double* partial, int nblk, double* out, hipStream_t s);
 hipError_t launch_kinetic_energy(int64_t nn, const double* U, const double* invWJ, double* partial, int nblk,
                                  double* ke, double* grad, hipStream_t s);
 hipError_t launch_check_state(int64_t nnodes, const double* U, double gamma, int32_t* count, hipStream_t s);
@@ -90,5 +127,13 @@ int ctx_kind(const nsfr_ctx* c);
 int64_t ctx_state_size(const nsfr_ctx* c);
 hipError_t launch_ensemble_stage(const StageArgs* table, const int2* items, int nitems, const int* kinds,
                                  size_t lds_bytes, int grid, hipStream_t s);
+
+// Gauss-Legendre variant (gl.hip): p = 2..5 with q = p + 1 .. p + 4 points
+hipError_t launch_gl_geometry(int p, int q, const GLOps* ops, int64_t E, const double* X, const double* Cline,
+                              double* Cq, double* Cf, double* invWJ, double* Xq, hipStream_t s);
+// the projection kernel, then the stage kernel (one element per workgroup)
+hipError_t launch_gl_stage(int p, int q, int variant, const StageArgs& a, const GLArgs& g, hipStream_t s);
+size_t gl_lds_bytes(int p, int q);   // dynamic LDS of the larger of the two kernels
+hipError_t gl_prepare(int p, int q);  // allow that much dynamic LDS on the current device
 
 }  // namespace nsfr

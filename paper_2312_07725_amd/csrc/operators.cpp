@@ -8,6 +8,8 @@
 #include "nsfr_host.h"
 
 #include <cmath>
+#include <cstring>
+#include <utility>
 
 namespace nsfr {
 
@@ -107,6 +109,145 @@ void build_ops(int p, double c, Ops& ops, HostOps& h) {
             ops.S1h[i][j] = in ? 0.5 * h.S1[i][j] : 0.0;
             ops.D[i][j] = in ? h.D[i][j] : 0.0;
         }
+    }
+}
+
+// ---- Gauss-Legendre operators (uncollocated quadrature; Sec. 3.3, Sec. 4
+// Eq. Fr projection with the basis evaluated at the quadrature points)
+
+static void solve_small(int n, double* A, double* B, int m) {
+    // B <- A^-1 B for an n x n matrix A and an n x m right-hand side
+    // (Gauss-Jordan elimination with partial pivoting; row-major).
+    for (int k = 0; k < n; ++k) {
+        int piv = k;
+        for (int i = k + 1; i < n; ++i)
+            if (std::fabs(A[i * n + k]) > std::fabs(A[piv * n + k])) piv = i;
+        if (piv != k) {
+            for (int j = 0; j < n; ++j) std::swap(A[k * n + j], A[piv * n + j]);
+            for (int j = 0; j < m; ++j) std::swap(B[k * m + j], B[piv * m + j]);
+        }
+        const double r = A[k * n + k];
+        for (int j = 0; j < n; ++j) A[k * n + j] /= r;
+        for (int j = 0; j < m; ++j) B[k * m + j] /= r;
+        for (int i = 0; i < n; ++i) {
+            if (i == k) continue;
+            const double f = A[i * n + k];
+            if (f == 0.0) continue;
+            for (int j = 0; j < n; ++j) A[i * n + j] -= f * A[k * n + j];
+            for (int j = 0; j < m; ++j) B[i * m + j] -= f * B[k * m + j];
+        }
+    }
+}
+
+static double lagrange(const double* x, int n, int j, double t) {
+    double v = 1.0;
+    for (int k = 0; k < n; ++k)
+        if (k != j) v *= (t - x[k]) / (x[j] - x[k]);
+    return v;
+}
+
+static double lagrange_d(const double* x, int n, int j, double t) {
+    double s = 0.0;
+    for (int m = 0; m < n; ++m) {
+        if (m == j) continue;
+        double v = 1.0 / (x[j] - x[m]);
+        for (int k = 0; k < n; ++k)
+            if (k != j && k != m) v *= (t - x[k]) / (x[j] - x[k]);
+        s += v;
+    }
+    return s;
+}
+
+void build_gl_ops(int p, int q, double c, const HostOps& h, GLOps& g) {
+    const int n = p + 1;
+    std::memset(&g, 0, sizeof(g));
+    g.p = p;
+    g.n = n;
+    g.q = q;
+    // Gauss-Legendre nodes: roots of P_q by Newton from Chebyshev guesses;
+    // weights 2 / ((1 - x^2) P_q'(x)^2), P_q' = q (x P_q - P_{q-1}) / (x^2 - 1)
+    for (int i = 0; i < q; ++i) {
+        double x = -std::cos(M_PI * (i + 0.75) / (q + 0.5));
+        for (int it = 0; it < 100; ++it) {
+            double Pq, Pm;
+            legendre_pair(q, x, Pq, Pm);
+            const double dP = q * (x * Pq - Pm) / (x * x - 1.0);
+            const double dx = Pq / dP;
+            x -= dx;
+            if (std::fabs(dx) < 1e-17) break;
+        }
+        g.xq[i] = x;
+    }
+    for (int i = 0; i < q / 2; ++i) {   // exact symmetry about 0
+        const double sx = 0.5 * (g.xq[q - 1 - i] - g.xq[i]);
+        g.xq[i] = -sx;
+        g.xq[q - 1 - i] = sx;
+    }
+    if (q % 2) g.xq[q / 2] = 0.0;
+    for (int i = 0; i < q; ++i) {
+        double Pq, Pm;
+        legendre_pair(q, g.xq[i], Pq, Pm);
+        const double dP = q * (g.xq[i] * Pq - Pm) / (g.xq[i] * g.xq[i] - 1.0);
+        g.wq[i] = 2.0 / ((1.0 - g.xq[i] * g.xq[i]) * dP * dP);
+    }
+    for (int i = 0; i < q / 2; ++i) {
+        const double w = 0.5 * (g.wq[i] + g.wq[q - 1 - i]);
+        g.wq[i] = g.wq[q - 1 - i] = w;
+    }
+    // basis at the quadrature points and its derivative
+    for (int i = 0; i < q; ++i)
+        for (int a = 0; a < n; ++a) {
+            g.chi[i * n + a] = lagrange(h.x, n, a, g.xq[i]);
+            g.chid[i * n + a] = lagrange_d(h.x, n, a, g.xq[i]);
+        }
+    // M = chi^T Wq chi; K = c (D^p)^T M D^p; projections
+    double M[MAXN * MAXN], K[MAXN * MAXN], Dp[MAXN * MAXN], T[MAXN * MAXN], R[MAXN * MAXQ];
+    for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b) {
+            double v = 0.0;
+            for (int i = 0; i < q; ++i) v += g.chi[i * n + a] * g.wq[i] * g.chi[i * n + b];
+            M[a * n + b] = v;
+        }
+    for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b) Dp[a * n + b] = (a == b) ? 1.0 : 0.0;
+    for (int k = 0; k < p; ++k) {
+        for (int a = 0; a < n; ++a)
+            for (int b = 0; b < n; ++b) {
+                double v = 0.0;
+                for (int m = 0; m < n; ++m) v += Dp[a * n + m] * h.D[m][b];
+                T[a * n + b] = v;
+            }
+        std::memcpy(Dp, T, sizeof(double) * n * n);
+    }
+    for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b) {
+            double v = 0.0;
+            for (int i = 0; i < n; ++i)
+                for (int j = 0; j < n; ++j) v += Dp[i * n + a] * M[i * n + j] * Dp[j * n + b];
+            K[a * n + b] = c * v;
+        }
+    for (int pass = 0; pass < 2; ++pass) {
+        double A[MAXN * MAXN];
+        for (int k = 0; k < n * n; ++k) A[k] = M[k] + (pass ? K[k] : 0.0);
+        for (int a = 0; a < n; ++a)
+            for (int i = 0; i < q; ++i) R[a * q + i] = g.chi[i * n + a] * g.wq[i];
+        solve_small(n, A, R, q);
+        double* out = pass ? g.pit : g.pi;
+        for (int k = 0; k < n * q; ++k) out[k] = R[k];
+    }
+    // flux basis: differentiation on the quadrature points and end values
+    double Dq[MAXQ * MAXQ];
+    for (int i = 0; i < q; ++i)
+        for (int j = 0; j < q; ++j) Dq[i * q + j] = lagrange_d(g.xq, q, j, g.xq[i]);
+    for (int i = 0; i < q; ++i) {
+        g.sqh[i * q + i] = 0.0;
+        for (int j = i + 1; j < q; ++j) {
+            const double v = 0.5 * (g.wq[i] * Dq[i * q + j] - Dq[j * q + i] * g.wq[j]);
+            g.sqh[i * q + j] = v;
+            g.sqh[j * q + i] = -v;
+        }
+        g.tl[i] = lagrange(g.xq, q, i, -1.0);
+        g.tr[i] = lagrange(g.xq, q, i, 1.0);
     }
 }
 

@@ -60,8 +60,8 @@ __global__ void advance_time_kernel(double* t, const double* dt) {
 }
 
 // 8 partial sums per block: [v.R, |v.R|, R0..R4, max|R|]
-__global__ __launch_bounds__(RB) void diag_partial(int64_t nn, const double* U, const double* R, double gamma,
-                                                   double* part) {
+__global__ __launch_bounds__(RB) void diag_partial(int64_t nn, const double* U, const double* V, const double* R,
+                                                   double gamma, double* part) {
     __shared__ double sh[RB];
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < nn; i += (int64_t)gridDim.x * RB) {
@@ -72,6 +72,8 @@ __global__ __launch_bounds__(RB) void diag_partial(int64_t nn, const double* U, 
         double beta = 0.5 * r / p;
         double s = log(p) - gamma * log(r);
         double ev[5] = {(gamma - s) / (gamma - 1.0) - beta * q2, 2 * beta * u, 2 * beta * v, 2 * beta * w, -2 * beta};
+        if (V)
+            for (int k = 0; k < 5; ++k) ev[k] = V[k * nn + i];
         for (int k = 0; k < 5; ++k) {
             double Rk = R[k * nn + i];
             double vr = ev[k] * Rk;
@@ -184,11 +186,11 @@ hipError_t launch_advance_time(double* t, const double* dt, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_diagnostics(int64_t nn, const double* U, const double* R, double gamma, double* partial, int nblk,
-                              double* out, hipStream_t s) {
+hipError_t launch_diagnostics(int64_t nn, const double* U, const double* V, const double* R, double gamma,
+                              double* partial, int nblk, double* out, hipStream_t s) {
     int nb = nblocks(nn);
     if (nb > nblk / 8) nb = nblk / 8;
-    diag_partial<<<nb, RB, 0, s>>>(nn, U, R, gamma, partial);
+    diag_partial<<<nb, RB, 0, s>>>(nn, U, V, R, gamma, partial);
     diag_final<<<1, RB, 0, s>>>(nb, partial, out);
     return hipGetLastError();
 }

@@ -44,7 +44,7 @@ def test_status_strings(L):
 
 @pytest.mark.parametrize("field,value", [("p", 1), ("p", 6), ("ne", (0, 2, 2)), ("hi", -1.0), ("gamma", 1.0),
                                          ("flux", 2), ("surface_diss", 3), ("source", -1), ("tile", 99),
-                                         ("c_fr", -1e-3)])
+                                         ("c_fr", -1e-3), ("quad", 2), ("overint", 4), ("overint", 1)])
 def test_create_rejects_bad_config(L, field, value):
     cfg = nsfr.make_config(3, 2)
     if field == "ne":
@@ -67,7 +67,15 @@ def test_null_arguments(L):
 
 
 def test_config_layout_matches_header():
-    # int32 p, int32 ne[3], 6 doubles, 4 int32 = 80 bytes, doubles 8-aligned
-    assert ctypes.sizeof(nsfr.Config) == 80
+    # int32 p, int32 ne[3], 6 doubles, 6 int32 = 88 bytes, doubles 8-aligned
+    assert ctypes.sizeof(nsfr.Config) == 88
     assert nsfr.Config.lo.offset == 16
     assert nsfr.Config.flux.offset == 64
+    assert nsfr.Config.quad.offset == 80 and nsfr.Config.overint.offset == 84
+
+
+def test_create_rejects_tile_with_gl_rule(L):
+    cfg = nsfr.make_config(3, 2, quad=1, tile=2)
+    ctx = ctypes.c_void_p()
+    assert L.nsfr_create(ctypes.byref(cfg), None, ctypes.byref(ctx)) == nsfr.NSFR_EINVAL
+    assert not ctx.value

@@ -171,3 +171,58 @@ def test_mms_order_of_accuracy_gl():
         errs.append(float(err[0]))
     rate = math.log2(errs[0] / errs[1])
     assert rate > p + 0.7, (errs, rate)
+
+
+# ---- the extended-precision coding of the uncollocated scheme (oracle.extended_gl)
+
+def test_extended_gl_rule_matches_numpy():
+    import numpy as np
+    from oracle import extended_gl as XG
+    for q in range(2, 10):
+        x, w = XG.gauss_legendre_x(q, np.float64)
+        xr, wr = np.polynomial.legendre.leggauss(q)
+        assert np.max(np.abs(x - xr)) < 1e-15 and np.max(np.abs(w - wr)) < 1e-15
+        xl, wl = XG.gauss_legendre_x(q)
+        assert abs(float(np.sum(wl)) - 2.0) < 1e-18
+        assert abs(float(np.sum(wl * xl ** (2 * q - 2))) - 2.0 / (2 * q - 1)) < 1e-18
+
+
+@pytest.mark.parametrize("p,overint,diss", [(2, 0, 0), (2, 2, 1), (3, 1, 2), (4, 0, 0)])
+def test_extended_gl_agrees_with_oracle(p, overint, diss):
+    """The numpy coding run in FP64 against oracle.gl (two independent codings
+    of the same definitions), rhs with c_HU and the source."""
+    import numpy as np
+    from oracle import extended_gl as XG
+    from oracle.operators import c_hu
+    c = c_hu(p)
+    s = gl.GLScheme(p, (2, 3, 2), beta=0.2, overint=overint, dissipation=diss, c=c, source=True)
+    x = XG.GLSchemeX(p, (2, 3, 2), beta=0.2, overint=overint, dissipation=diss, c=c, source=True, dt=np.float64)
+    U = inputs.perturbed_state(s.X, seed=p + 10)
+    a = s.rhs(U, 0.3).numpy()
+    b = x.rhs(U.numpy(), 0.3)
+    assert np.max(np.abs(a - b)) < 1e-12 * np.max(np.abs(a))
+
+
+def test_extended_gl_sampled_equals_full():
+    import numpy as np
+    from oracle import extended_gl as XG
+    U = inputs.perturbed_state(gl.GLScheme(3, (3, 2, 3), beta=0.2).X, seed=5).numpy()
+    full = XG.GLSchemeX(3, (3, 2, 3), beta=0.2, overint=1, dissipation=2).residual(U)
+    ids = [0, 7, 17, 4]
+    samp = XG.GLSchemeX(3, (3, 2, 3), beta=0.2, overint=1, dissipation=2, elements=ids).residual(U)
+    assert np.max(np.abs(full[:, ids] - samp)) == 0.0
+
+
+def test_extended_gl_conservation_and_entropy_long_double():
+    """Conservation and entropy conservation at long-double round-off (an
+    FP64-only coding mistake would not show at this level)."""
+    import numpy as np
+    from oracle import extended_gl as XG
+    x = XG.GLSchemeX(2, (2, 2, 3), beta=0.2, overint=1)
+    U = inputs.perturbed_state(gl.GLScheme(2, (2, 2, 3), beta=0.2).X, seed=3).numpy()
+    R = x.residual(U)
+    tot = np.abs(R.reshape(5, -1).sum(1))
+    mag = np.abs(R).reshape(5, -1).sum(1)
+    assert np.all(tot <= 1e-17 * mag)
+    v = x.projected_entropy_variables(U)
+    assert abs(float(np.sum(v * R))) < 1e-17 * float(np.sum(np.abs(v * R)))
