@@ -24,7 +24,8 @@ Layout as in the other oracles: state (5, E, n, n, n) indexed [s, e, c, b, a]
 with a the xi index."""
 import numpy as np
 
-from .extended import LD, MeshX, Ops1D, _entropy_vars, _legendre, _pi, _solve, ec_flux, llf, mms_source, roe
+from .extended import (LD, MeshX, Ops1D, _entropy_vars, _legendre, _pi, _solve, ec_flux, llf, mms_source, primitives,
+                       roe)
 
 
 def gauss_legendre_x(q, dt=LD):
@@ -239,3 +240,105 @@ class GLSchemeX:
 
     def rhs(self, U, t=0.0):
         return -self.apply_inverse_mass(self.residual(U, t))
+
+
+# ---------------------------------------------------------------------------
+# Conservative strong DG on the same rule (Sec. 3.1 Eq. cons DG strong) with
+# Roe's flux (Sec. 7.4): the baseline of the paper's cost comparison
+# ---------------------------------------------------------------------------
+
+def physical_flux(U, gamma):
+    """f_k(U), shape (3, 5, ...)."""
+    rho, vel, p, _ = primitives(U, gamma)
+    out = []
+    for k in range(3):
+        f = [U[0] * vel[k], U[1] * vel[k], U[2] * vel[k], U[3] * vel[k], (U[4] + p) * vel[k]]
+        f[1 + k] = f[1 + k] + p
+        out.append(np.stack(f))
+    return np.stack(out)
+
+
+def roe_flux(Ua, Ub, N, gamma):
+    """Roe's flux N . f* = (f_a + f_b) . N / 2 - |N| |A^| (U_b - U_a) / 2 with
+    |A^| dU written as the sum over the acoustic, entropy and shear waves at
+    Roe's sqrt(rho)-weighted average."""
+    ra, va, pa, _ = primitives(Ua, gamma)
+    rb, vb, pb, _ = primitives(Ub, gamma)
+    nn = np.sqrt(N[0] ** 2 + N[1] ** 2 + N[2] ** 2)
+    n = [N[k] / nn for k in range(3)]
+    sa, sb = np.sqrt(ra), np.sqrt(rb)
+    u = [(sa * va[k] + sb * vb[k]) / (sa + sb) for k in range(3)]
+    H = (sa * (Ua[4] + pa) / ra + sb * (Ub[4] + pb) / rb) / (sa + sb)
+    q2 = u[0] ** 2 + u[1] ** 2 + u[2] ** 2
+    c2 = (gamma - 1) * (H - q2 / 2)
+    c = np.sqrt(c2)
+    rho = sa * sb
+    un = u[0] * n[0] + u[1] * n[1] + u[2] * n[2]
+    du = [vb[k] - va[k] for k in range(3)]
+    dun = du[0] * n[0] + du[1] * n[1] + du[2] * n[2]
+    dp = pb - pa
+    one = np.ones_like(rho)
+    waves = []
+    for sg in (-1, 1):
+        waves.append(((dp + sg * rho * c * dun) / (2 * c2) * np.abs(un + sg * c),
+                      [one, u[0] + sg * c * n[0], u[1] + sg * c * n[1], u[2] + sg * c * n[2], H + sg * c * un]))
+    waves.append(((rb - ra - dp / c2) * np.abs(un), [one, u[0], u[1], u[2], q2 / 2]))
+    D = np.zeros_like(Ua)
+    for a, r in waves:
+        for i in range(5):
+            D[i] = D[i] + a * r[i]
+    b = rho * np.abs(un)
+    for k in range(3):
+        D[1 + k] = D[1 + k] + b * (du[k] - dun * n[k])
+    D[4] = D[4] + b * (u[0] * du[0] + u[1] * du[1] + u[2] * du[2] - un * dun)
+    fa, fb = physical_flux(Ua, gamma), physical_flux(Ub, gamma)
+    return sum((fa[k] + fb[k]) * N[k] for k in range(3)) / 2 - nn * D / 2
+
+
+class DGSchemeX(GLSchemeX):
+    """Conservative strong DG with Roe's flux on the Gauss-Legendre rule, in
+    type dt (same mesh, operators, sampling and mass inverse as GLSchemeX)."""
+
+    def __init__(self, p, ne, lo=0.0, hi=None, beta=0.0, l=None, gamma=1.4, c=0.0, source=False, overint=0,
+                 dt=LD, elements=None):
+        super().__init__(p, ne, lo=lo, hi=hi, beta=beta, l=l, gamma=gamma, c=c, source=source, overint=overint,
+                         dt=dt, elements=elements)
+        self.Dq = lagrange_derivative(self.ops.xq)
+
+    def residual(self, U, t=0.0):
+        m, o, g = self.mesh, self.ops, self.gamma
+        U = np.asarray(U).astype(self.dt)[:, m.ids]
+        TL = self.tloc
+        UT = U[:, TL]
+        F = physical_flux(_tensor(o.chi, UT), g)
+        wq = o.wq
+        wperp = wq[:, None] * wq[None, :]
+        uf = {(k, s): _slab_interp(o.chi, _slab(U, k, s)) for k in range(3) for s in (-1, 1)}
+        Rv = np.zeros_like(F[0])
+        Rf = {}
+        for k in range(3):
+            Ck = self.Cq[:, k][:, TL]
+            fr = sum(Ck[mm][None] * F[mm] for mm in range(3))
+            Fk = np.moveaxis(fr, -1 - k, -1)
+            Rk = (Fk @ self.Dq.T) * wq * wperp[..., None]
+            Rv = Rv + np.moveaxis(Rk, -1, -1 - k)
+            for s, tv in ((1, o.tR), (-1, o.tL)):
+                nb = m.loc[m.neighbour_ids(self.target, k, s)]
+                Co = self.Cf[(k, s)][:, TL]
+                Cb = self.Cf[(k, -s)][:, nb]
+                Ns = [s * (Co[i] + Cb[i]) / 2 for i in range(3)]
+                fs = roe_flux(uf[(k, s)][:, TL], uf[(k, -s)][:, nb], Ns, g)
+                Rf[(k, s)] = (fs - s * np.einsum("a,...a->...", tv, Fk)) * wperp
+        if self.source:
+            Rv = Rv - self.WJq[TL] * mms_source(self.Xq[:, TL], t, g, self.dt)
+        R = _tensor(o.chi.T, Rv)
+        for (k, s), S in Rf.items():
+            add = np.einsum("ji,lk,...lj->...ki", o.chi, o.chi, S)
+            idx = -1 if s > 0 else 0
+            if k == 0:
+                R[..., idx] += add
+            elif k == 1:
+                R[..., idx, :] += add
+            else:
+                R[..., idx, :, :] += add
+        return R

@@ -203,6 +203,52 @@ def roe_dissipation(Ua, Ub, N, gamma):
     return -0.5 * nn * out
 
 
+def roe_flux(Ua, Ub, N, gamma):
+    """Roe's approximate Riemann solver (Roe 1981), the surface numerical flux
+    of the conservative DG scheme the paper compares against (Sec. 7.4):
+    N . f* = (f(U_a) + f(U_b)) . N / 2 - |N| |A^| (U_b - U_a) / 2, with A^ the
+    flux Jacobian in n = N / |N| at Roe's average (sqrt(rho)-weighted velocity
+    and total enthalpy H = (rho e + p) / rho; rho^ = sqrt(rho_a rho_b)), so that
+    A^ (U_b - U_a) = (f(U_b) - f(U_a)) . n. |A^| dU is written wave by wave:
+      acoustic n -+ c:  strength (dp -+ rho^ c dun) / (2 c^2),
+                        r = [1, u -+ c n, H -+ c u.n];
+      entropy:          strength drho - dp / c^2, r = [1, u, |u|^2 / 2];
+      shear:            rho^ [0, du - dun n, u . du - u.n dun], speed u.n;
+    c^2 = (gamma - 1)(H - |u|^2 / 2). No entropy fix (the compared flows are
+    subsonic). Real tensors only."""
+    ra, va, pa, _ = primitives(Ua, gamma)
+    rb, vb, pb, _ = primitives(Ub, gamma)
+    nn = torch.sqrt(N[0] ** 2 + N[1] ** 2 + N[2] ** 2)
+    n = [N[k] / nn for k in range(3)]
+    sa, sb = torch.sqrt(ra), torch.sqrt(rb)
+    w = 1.0 / (sa + sb)
+    u = [(sa * va[k] + sb * vb[k]) * w for k in range(3)]
+    Ha, Hb = (Ua[4] + pa) / ra, (Ub[4] + pb) / rb
+    H = (sa * Ha + sb * Hb) * w
+    q2 = u[0] ** 2 + u[1] ** 2 + u[2] ** 2
+    c = torch.sqrt((gamma - 1.0) * (H - 0.5 * q2))
+    rho = sa * sb
+    un = u[0] * n[0] + u[1] * n[1] + u[2] * n[2]
+    dr, dp = rb - ra, pb - pa
+    du = [vb[k] - va[k] for k in range(3)]
+    dun = du[0] * n[0] + du[1] * n[1] + du[2] * n[2]
+    one = torch.ones_like(rho)
+    d = torch.zeros_like(Ua)
+    for sg in (-1.0, 1.0):
+        a = (dp + sg * rho * c * dun) / (2.0 * c * c) * (un + sg * c).abs()
+        r = [one] + [u[k] + sg * c * n[k] for k in range(3)] + [H + sg * c * un]
+        d = d + torch.stack([a * r[i] for i in range(5)])
+    a = (dr - dp / (c * c)) * un.abs()
+    d = d + torch.stack([a, a * u[0], a * u[1], a * u[2], a * 0.5 * q2])
+    sh = [du[k] - dun * n[k] for k in range(3)]
+    b = rho * un.abs()
+    d = d + torch.stack([0.0 * b, b * sh[0], b * sh[1], b * sh[2], b * (u[0] * du[0] + u[1] * du[1] + u[2] * du[2]
+                                                                      - un * dun)])
+    fa, fb = physical_flux(Ua, gamma), physical_flux(Ub, gamma)
+    central = 0.5 * sum((fa[k] + fb[k]) * N[k] for k in range(3))
+    return central - 0.5 * nn * d
+
+
 def surface_dissipation(kind, gamma):
     """The dissipation term added to the EC surface flux: None for kind 0 /
     False, local Lax-Friedrichs for kind 1 / True / "llf", the entropy-stable
