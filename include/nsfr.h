@@ -82,8 +82,17 @@ typedef struct {
                              the solution still stored as values at the LGL nodes, with the
                              entropy projection u~ = u(chi Pi v(chi u)) feeding the
                              two-point fluxes of the hybridised operator                 */
-    int32_t overint;      /* extra quadrature points per direction (overintegration),
-                             0..3; must be 0 with quad = 0                               */
+    int32_t overint;      /* extra quadrature points per direction (overintegration):
+                             0..3 for NSFR, 0..p+1 for DG (p + 1 extra points give the
+                             2 (p + 1)-point rule of the paper's overintegrated DG);
+                             must be 0 with quad = 0                                     */
+    int32_t scheme;       /* 0: NSFR (Eq. NSFR); 1: conservative DG in strong form (Sec.
+                             3.1 Eq. cons DG strong) with Roe's surface flux, the
+                             baseline of Sec. 7.4: u interpolated to the points (no
+                             entropy projection), the contravariant flux C^T f(u)
+                             differentiated in the flux basis, N . f* - n . phi_f f^r on
+                             the faces, the same weight-adjusted inverse. Needs quad = 1
+                             and surface_diss = 0; flux is ignored                       */
 } nsfr_config;
 
 typedef struct nsfr_ctx nsfr_ctx;
@@ -96,8 +105,9 @@ typedef struct nsfr_ctx nsfr_ctx;
  * cofactors, x and 1/(W J) at the volume points and the cofactors at the face
  * points (the LGL-grid polynomials, so the discrete GCL holds there too).
  * hip_stream may be NULL (default stream). Errors: NSFR_EINVAL (p outside
- * 2..5, ne < 1, hi <= lo, gamma <= 1, flux/surface_diss/source/quad/overint
- * out of range, negative tile, tile with quad = 1, overint with quad = 0),
+ * 2..5, ne < 1, hi <= lo, gamma <= 1, flux/surface_diss/source/quad/overint/
+ * scheme out of range, negative tile, tile with quad = 1, overint with
+ * quad = 0, DG with quad = 0 or surface_diss != 0),
  * NSFR_ENOTSUP if the Gauss-Legendre kernels need more LDS per workgroup than
  * the device allows, NSFR_ENOMEM, NSFR_EHIP, NSFR_EUNPHYSICAL if some node or
  * quadrature point has J <= 0. */

@@ -80,7 +80,13 @@ static nsfr_status validate(const nsfr_config* c) {
     if (c->source < 0 || c->source > 1) return bad("source must be 0 or 1");
     if (c->tile < 0 || c->tile > max_epb(c->p)) return bad("tile out of range for this p");
     if (c->quad < 0 || c->quad > 1) return bad("quad must be 0 (LGL collocated) or 1 (Gauss-Legendre)");
-    if (c->overint < 0 || c->overint > MAX_OVERINT) return bad("overint must be in 0..3");
+    if (c->scheme < 0 || c->scheme > 1) return bad("scheme must be 0 (NSFR) or 1 (conservative DG)");
+    if (c->scheme == 1 && c->quad != 1) return bad("conservative DG runs on the Gauss-Legendre rule (quad = 1)");
+    if (c->scheme == 1 && c->surface_diss != 0)
+        return bad("conservative DG uses Roe's surface flux; surface_diss must be 0");
+    const int omax = c->scheme == 1 ? c->p + 1 : MAX_OVERINT;
+    if (c->overint < 0 || c->overint > omax)
+        return bad("overint must be in 0.." + std::to_string(omax) + (c->scheme == 1 ? " for DG" : " for NSFR"));
     if (c->quad == 0 && c->overint != 0) return bad("overintegration needs the Gauss-Legendre rule (quad = 1)");
     if (c->quad == 1 && c->tile != 0) return bad("the Gauss-Legendre kernels take no tile (tile must be 0)");
     return NSFR_OK;
@@ -142,7 +148,7 @@ static GLArgs gl_args(const nsfr_ctx* c) {
 }
 
 static nsfr_status stage(nsfr_ctx* c, StageArgs& a) {
-    hipError_t e = c->cfg.quad ? launch_gl_stage(c->p, c->q, c->cfg.flux, a, gl_args(c), c->stream)
+    hipError_t e = c->cfg.quad ? launch_gl_stage(c->cfg.scheme == 1, c->p, c->q, c->cfg.flux, a, gl_args(c), c->stream)
                                : launch_stage(c->p, c->cfg.c_fr != 0.0, c->cfg.flux, a, c->stream);
     if (e != hipSuccess) {
         set_error(std::string("stage kernel launch: ") + hipGetErrorString(e));
@@ -197,16 +203,17 @@ const char* nsfr_last_error(void) { return g_last_error.c_str(); }
 static nsfr_status gl_setup(nsfr_ctx* c) {
     const int q = c->n + c->cfg.overint;
     c->q = q;
-    const size_t need = gl_lds_bytes(c->p, q);
+    const bool dg = c->cfg.scheme == 1;
+    const size_t need = gl_lds_bytes(dg, c->p, q);
     int lds_max = 0;
     HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, c->dev));
     if (need > (size_t)lds_max) {
-        set_error("Gauss-Legendre kernels for p = " + std::to_string(c->p) + ", " + std::to_string(q) +
+        set_error(std::string(dg ? "DG" : "NSFR") + " Gauss-Legendre kernels for p = " + std::to_string(c->p) + ", " + std::to_string(q) +
                   " points need " + std::to_string(need) + " bytes of LDS per workgroup; the device allows " +
                   std::to_string(lds_max));
         return NSFR_ENOTSUP;
     }
-    HIP_TRY(gl_prepare(c->p, q));
+    HIP_TRY(gl_prepare(dg, c->p, q));
     GLOps h;
     build_gl_ops(c->p, q, c->cfg.c_fr, c->hops, h);
     const size_t E = (size_t)c->E, q2 = (size_t)q * q, q3 = q2 * q;
@@ -489,10 +496,11 @@ nsfr_status nsfr_diagnostics(nsfr_ctx* c, const double* U, double t, double* out
     if (!c || !aligned(U) || !aligned(out)) return bad("null or misaligned argument");
     nsfr_status st = nsfr_residual(c, U, c->wsR, t);
     if (st) return st;
-    // Gauss-Legendre: the entropy rate pairs R with the projected entropy
-    // variables that the residual evaluation left in vhat
-    HIP_TRY(launch_diagnostics((int64_t)c->E * c->n3, U, c->cfg.quad ? c->vhat : nullptr, c->wsR, c->cfg.gamma,
-                               c->red, c->nred, out, c->stream));
+    // NSFR on the Gauss-Legendre rule: the entropy rate pairs R with the
+    // projected entropy variables that the residual evaluation left in vhat
+    const bool proj = c->cfg.quad && c->cfg.scheme == 0;
+    HIP_TRY(launch_diagnostics((int64_t)c->E * c->n3, U, proj ? c->vhat : nullptr, c->wsR, c->cfg.gamma, c->red,
+                               c->nred, out, c->stream));
     return NSFR_OK;
 }
 

@@ -24,11 +24,21 @@
 //     ends, and the surface numerical flux at those ends), the transpose
 //     interpolation of the volume and face residuals to the coefficients, the
 //     weight-adjusted inverse, and the RK combination.
+//
+// The conservative DG scheme the paper compares against (Sec. 3.1 Eq. cons
+// DG strong, Sec. 7.4: same rule, Roe's surface flux, an overintegrated
+// variant) runs on the same operators and metric terms with two kernels of
+// its own: gl_project_kernel<.., DG = true> writes the interpolated
+// conservative states at the face points, and dg_stage_kernel evaluates the
+// strong-form volume term chi^T W Dphi_k f^r_k, the surface term
+// chi_f^T W_f [N . f* - n . phi_f f^r] and the same mass inverse and RK
+// combination.
 #include "nsfr_host.h"
 
 namespace nsfr {
 
-constexpr int GL_BLOCK = 256;
+constexpr int GL_BLOCK = 256;   // projection kernels; NSFR stage (3 q^2 <= 243 line threads)
+constexpr int DG_BLOCK = 512;   // DG stage (3 q^2 <= 432 line threads at q = 12)
 
 // ---- sum-factorised 1D operator in LDS: dst = M applied along axis AX of
 // src (dims S0 x S1 x S2, x fastest) for `ns` states; M is OUT x IN
@@ -169,7 +179,7 @@ __global__ void gl_face_geometry_kernel(const GLOps* __restrict__ ops, int64_t E
 }
 
 // ---- entropy projection: v^ = Pi v(chi u^) and v^ at every face point
-template <int N, int Q>
+template <int N, int Q, bool DG>
 __global__ __launch_bounds__(GL_BLOCK) void gl_project_kernel(const GLOps* __restrict__ ops, int64_t E,
                                                               const double* __restrict__ U, double gamma,
                                                               double* vhat, double* ft) {
@@ -177,8 +187,8 @@ __global__ __launch_bounds__(GL_BLOCK) void gl_project_kernel(const GLOps* __res
     extern __shared__ double lds[];
     double* mchi = lds;              // Q x N
     double* mpi = mchi + Q * N;      // N x Q
-    double* A = mpi + N * Q;         // 5 Q^3
-    double* B = A + 5 * Q3;          // 5 Q^3
+    double* A = mpi + N * Q;         // 5 Q^3 (DG: 5 N^3)
+    double* B = A + 5 * Q3;          // 5 Q^3 (not used by DG)
     const int tid = threadIdx.x;
     const int64_t e = blockIdx.x;
     const int64_t SE = E * N3;
@@ -192,32 +202,34 @@ __global__ __launch_bounds__(GL_BLOCK) void gl_project_kernel(const GLOps* __res
         A[i] = U[s * SE + e * N3 + nd];
     }
     __syncthreads();
-    lds_pass<N, N, N, 0, Q, false>(A, B, mchi, 5);
-    __syncthreads();
-    lds_pass<Q, N, N, 1, Q, false>(B, A, mchi, 5);
-    __syncthreads();
-    lds_pass<Q, Q, N, 2, Q, false>(A, B, mchi, 5);
-    __syncthreads();
-    for (int t = tid; t < Q3; t += blockDim.x) {
-        double u[5], v[5];
+    if constexpr (!DG) {
+        lds_pass<N, N, N, 0, Q, false>(A, B, mchi, 5);
+        __syncthreads();
+        lds_pass<Q, N, N, 1, Q, false>(B, A, mchi, 5);
+        __syncthreads();
+        lds_pass<Q, Q, N, 2, Q, false>(A, B, mchi, 5);
+        __syncthreads();
+        for (int t = tid; t < Q3; t += blockDim.x) {
+            double u[5], v[5];
 #pragma unroll
-        for (int s = 0; s < 5; ++s) u[s] = B[s * Q3 + t];
-        entropy_vars(u, gm1, gamma, v);
+            for (int s = 0; s < 5; ++s) u[s] = B[s * Q3 + t];
+            entropy_vars(u, gm1, gamma, v);
 #pragma unroll
-        for (int s = 0; s < 5; ++s) B[s * Q3 + t] = v[s];
+            for (int s = 0; s < 5; ++s) B[s * Q3 + t] = v[s];
+        }
+        __syncthreads();
+        lds_pass<Q, Q, Q, 2, N, false>(B, A, mpi, 5);
+        __syncthreads();
+        lds_pass<Q, Q, N, 1, N, false>(A, B, mpi, 5);
+        __syncthreads();
+        lds_pass<Q, N, N, 0, N, false>(B, A, mpi, 5);
+        __syncthreads();
+        for (int i = tid; i < 5 * N3; i += blockDim.x) {
+            const int s = i / N3, nd = i - s * N3;
+            vhat[s * SE + e * N3 + nd] = A[i];
+        }
     }
-    __syncthreads();
-    lds_pass<Q, Q, Q, 2, N, false>(B, A, mpi, 5);
-    __syncthreads();
-    lds_pass<Q, Q, N, 1, N, false>(A, B, mpi, 5);
-    __syncthreads();
-    lds_pass<Q, N, N, 0, N, false>(B, A, mpi, 5);
-    __syncthreads();
-    for (int i = tid; i < 5 * N3; i += blockDim.x) {
-        const int s = i / N3, nd = i - s * N3;
-        vhat[s * SE + e * N3 + nd] = A[i];
-    }
-    // v^ at the face points: the end slab of the coefficients, interpolated in
+    // v^ (DG: u) at the face points: the end slab of the coefficients, interpolated in
     // the two tangential directions
     for (int it = tid; it < 6 * 5 * Q2; it += blockDim.x) {
         const int f = it / (5 * Q2), r = it - f * 5 * Q2;
@@ -529,6 +541,309 @@ __global__ __launch_bounds__(GL_BLOCK) void gl_stage_kernel(StageArgs A, GLArgs 
     }
 }
 
+// ---- conservative DG (Sec. 3.1 Eq. cons DG strong)
+
+// Roe's flux N . f* = (f(A) + f(B)) . N / 2 - |N| |A^| (B - A) / 2 at Roe's
+// average (sqrt(rho)-weighted velocity and total enthalpy, rho^ =
+// sqrt(rho_A rho_B)); |A^| dU as the sum over the two acoustic waves, the
+// entropy wave and the shear waves (Roe 1981; Sec. 7.4 uses it for DG). The
+// momentum flux carries p - p_ref (the constant p_ref N terms cancel in the
+// residual by the discrete GCL, as in the NSFR kernels).
+__device__ __forceinline__ void roe_flux_dev(const double A[5], const double B[5], double nx, double ny, double nz,
+                                             double gamma, double pref, double F[5]) {
+    const double gm1 = gamma - 1.0;
+    const double ra = A[0], rb = B[0];
+    const double ira = 1.0 / ra, irb = 1.0 / rb;
+    const double ua = A[1] * ira, va = A[2] * ira, wa = A[3] * ira;
+    const double ub = B[1] * irb, vb = B[2] * irb, wb = B[3] * irb;
+    const double pa = gm1 * (A[4] - 0.5 * (A[1] * ua + A[2] * va + A[3] * wa));
+    const double pb = gm1 * (B[4] - 0.5 * (B[1] * ub + B[2] * vb + B[3] * wb));
+    const double una = ua * nx + va * ny + wa * nz, unb = ub * nx + vb * ny + wb * nz;
+    // central part (momentum with p - p_ref)
+    const double pda = pa - pref, pdb = pb - pref;
+    F[0] = 0.5 * (A[0] * una + B[0] * unb);
+    F[1] = 0.5 * (A[1] * una + B[1] * unb + (pda + pdb) * nx);
+    F[2] = 0.5 * (A[2] * una + B[2] * unb + (pda + pdb) * ny);
+    F[3] = 0.5 * (A[3] * una + B[3] * unb + (pda + pdb) * nz);
+    F[4] = 0.5 * ((A[4] + pa) * una + (B[4] + pb) * unb);
+    // Roe average
+    const double nn = sqrt(nx * nx + ny * ny + nz * nz);
+    const double inn = 1.0 / nn;
+    const double ex = nx * inn, ey = ny * inn, ez = nz * inn;
+    const double sa = sqrt(ra), sb = sqrt(rb);
+    const double iw = 1.0 / (sa + sb);
+    const double u = (sa * ua + sb * ub) * iw, v = (sa * va + sb * vb) * iw, w = (sa * wa + sb * wb) * iw;
+    const double H = (sa * (A[4] + pa) * ira + sb * (B[4] + pb) * irb) * iw;
+    const double q2 = u * u + v * v + w * w;
+    const double c2 = gm1 * (H - 0.5 * q2);
+    const double c = sqrt(c2), ic2 = 1.0 / c2;
+    const double rho = sa * sb;
+    const double un = u * ex + v * ey + w * ez;
+    const double du = ub - ua, dv = vb - va, dw = wb - wa;
+    const double dun = du * ex + dv * ey + dw * ez;
+    const double dp = pdb - pda;
+    double D[5];
+    {   // entropy wave
+        const double a = (rb - ra - dp * ic2) * fabs(un);
+        D[0] = a;
+        D[1] = a * u;
+        D[2] = a * v;
+        D[3] = a * w;
+        D[4] = a * 0.5 * q2;
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {   // acoustic waves u.n -+ c
+        const double sg = k ? 1.0 : -1.0;
+        const double a = (dp + sg * rho * c * dun) * (0.5 * ic2) * fabs(un + sg * c);
+        D[0] += a;
+        D[1] += a * (u + sg * c * ex);
+        D[2] += a * (v + sg * c * ey);
+        D[3] += a * (w + sg * c * ez);
+        D[4] += a * (H + sg * c * un);
+    }
+    {   // shear waves
+        const double b = rho * fabs(un);
+        const double sx = du - dun * ex, sy = dv - dun * ey, sz = dw - dun * ez;
+        D[1] += b * sx;
+        D[2] += b * sy;
+        D[3] += b * sz;
+        D[4] += b * (u * du + v * dv + w * dw - un * dun);
+    }
+    const double k = 0.5 * nn;
+#pragma unroll
+    for (int s = 0; s < 5; ++s) F[s] -= k * D[s];
+}
+
+// One element per workgroup. LDS: the 1D operators, VA [5][q^3] (states at
+// the volume points, then the volume residual, then ping-pong), VB [5][q^2 n]
+// (ping-pong), RF [6][5][q^2] (face-point residuals).
+template <int N, int Q>
+__global__ __launch_bounds__(DG_BLOCK) void dg_stage_kernel(StageArgs A, GLArgs G) {
+    constexpr int N2 = N * N, N3 = N2 * N, Q2 = Q * Q, Q3 = Q2 * Q;
+    extern __shared__ double lds[];
+    double* mchi = lds;               // Q x N
+    double* mpit = mchi + Q * N;      // N x Q
+    double* mdq = mpit + N * Q;       // Q x Q
+    double* mtl = mdq + Q2;           // Q
+    double* mtr = mtl + Q;            // Q
+    double* mw = mtr + Q;             // Q
+    double* VA = mw + Q;              // 5 Q^3
+    double* VB = VA + 5 * Q3;         // 5 Q^2 N
+    double* RF = VB + 5 * Q2 * N;     // [6][5][Q^2]
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int64_t e = blockIdx.x;
+    const int64_t E = A.geo.E;
+    const int64_t SE = E * N3;
+    const double gamma = A.gamma, gm1 = gamma - 1.0;
+    const double pref = reference_pressure(A.Uin, SE, gm1);
+    const GLOps* ops = G.ops;
+    for (int i = tid; i < Q * N; i += nth) {
+        mchi[i] = ops->chi[i];
+        mpit[i] = ops->pit[i];
+    }
+    for (int i = tid; i < Q2; i += nth) mdq[i] = ops->dq[i];
+    for (int i = tid; i < Q; i += nth) {
+        mtl[i] = ops->tl[i];
+        mtr[i] = ops->tr[i];
+        mw[i] = ops->wq[i];
+    }
+    // 1. u at the volume points: chi along x, y, z (VB -> VA -> VB -> VA)
+    for (int i = tid; i < 5 * N3; i += nth) {
+        const int s = i / N3, nd = i - s * N3;
+        VB[i] = A.Uin[s * SE + e * N3 + nd];
+    }
+    __syncthreads();
+    lds_pass<N, N, N, 0, Q, false>(VB, VA, mchi, 5);
+    __syncthreads();
+    lds_pass<Q, N, N, 1, Q, false>(VA, VB, mchi, 5);
+    __syncthreads();
+    lds_pass<Q, Q, N, 2, Q, false>(VB, VA, mchi, 5);
+    __syncthreads();
+
+    // 2. one thread per line: the contravariant flux f^r_k at the line's points,
+    //    its flux-basis derivative (R_v[a] = w_a W_perp sum_b Dq[a][b] f^r_k(b)),
+    //    its values at the two ends, and Roe's flux with the neighbour there
+    const int lt = tid;
+    const bool active = lt < 3 * Q2;
+    const int dir = active ? lt / Q2 : 0;
+    const int l = active ? lt - dir * Q2 : 0;
+    const int t1 = l % Q, t2 = l / Q;
+    const int base = dir == 0 ? Q * t1 + Q2 * t2 : (dir == 1 ? t1 + Q2 * t2 : t1 + Q * t2);
+    const int stride = dir == 0 ? 1 : (dir == 1 ? Q : Q2);
+    double Rv[5][Q], Rf[2][5];
+#pragma unroll
+    for (int s = 0; s < 5; ++s) {
+#pragma unroll
+        for (int a = 0; a < Q; ++a) Rv[s][a] = 0.0;
+        Rf[0][s] = Rf[1][s] = 0.0;
+    }
+    if (active) {
+        const double* Cl = G.geo.Cq + (int64_t)(3 * dir) * E * Q3 + e * Q3 + l;
+        const int64_t CS = E * Q3;
+#pragma unroll
+        for (int b = 0; b < Q; ++b) {
+            const int t = base + b * stride;
+            const double r = VA[t], m1 = VA[Q3 + t], m2 = VA[2 * Q3 + t], m3 = VA[3 * Q3 + t], en = VA[4 * Q3 + t];
+            const double cx = Cl[b * Q2], cy = Cl[CS + b * Q2], cz = Cl[2 * CS + b * Q2];
+            const double ir = 1.0 / r;
+            const double un = (m1 * cx + m2 * cy + m3 * cz) * ir;
+            const double p = gm1 * (en - 0.5 * (m1 * m1 + m2 * m2 + m3 * m3) * ir);
+            const double pd = p - pref;
+            const double fr[5] = {r * un, m1 * un + pd * cx, m2 * un + pd * cy, m3 * un + pd * cz, (en + p) * un};
+#pragma unroll
+            for (int s = 0; s < 5; ++s) {
+#pragma unroll
+                for (int a = 0; a < Q; ++a) Rv[s][a] = __builtin_fma(mdq[a * Q + b], fr[s], Rv[s][a]);
+                Rf[0][s] = __builtin_fma(mtl[b], fr[s], Rf[0][s]);
+                Rf[1][s] = __builtin_fma(mtr[b], fr[s], Rf[1][s]);
+            }
+        }
+        // face terms: N . f* - s t . f^r (s = -1 at the left end, +1 at the right)
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const int f = 2 * dir + side;
+            const double sg = side ? 1.0 : -1.0;
+            const int64_t FS = E * Q2;
+            const double* Cfo = G.geo.Cf + ((int64_t)(f * 3) * E + e) * Q2 + l;
+            const int en = A.geo.nbr[(int64_t)f * E + e];
+            const int fn = 2 * dir + (1 - side);
+            const double* Cfn = G.geo.Cf + ((int64_t)(fn * 3) * E + en) * Q2 + l;
+            const double nx = 0.5 * sg * (Cfo[0] + Cfn[0]), ny = 0.5 * sg * (Cfo[FS] + Cfn[FS]),
+                         nz = 0.5 * sg * (Cfo[2 * FS] + Cfn[2 * FS]);
+            double uo[5], un[5], F[5];
+#pragma unroll
+            for (int s = 0; s < 5; ++s) {
+                uo[s] = G.ft[((int64_t)(f * 5 + s) * E + e) * Q2 + l];
+                un[s] = G.ft[((int64_t)(fn * 5 + s) * E + en) * Q2 + l];
+            }
+            roe_flux_dev(uo, un, nx, ny, nz, gamma, pref, F);
+#pragma unroll
+            for (int s = 0; s < 5; ++s) Rf[side][s] = F[s] - sg * Rf[side][s];
+        }
+    }
+    __syncthreads();   // the volume states (VA) are no longer read
+    const double wperp = mw[t1] * mw[t2];
+    for (int ph = 0; ph < 3; ++ph) {
+        if (active && dir == ph) {
+#pragma unroll
+            for (int s = 0; s < 5; ++s)
+#pragma unroll
+                for (int a = 0; a < Q; ++a) {
+                    const double v = Rv[s][a] * (mw[a] * wperp);
+                    double* x = VA + s * Q3 + base + a * stride;
+                    if (ph == 0) *x = v;
+                    else *x += v;
+                }
+        }
+        __syncthreads();
+    }
+    if (active) {
+#pragma unroll
+        for (int side = 0; side < 2; ++side)
+#pragma unroll
+            for (int s = 0; s < 5; ++s) RF[((2 * dir + side) * 5 + s) * Q2 + l] = Rf[side][s] * wperp;
+    }
+    const int mode = A.mode;
+    double dt = 0.0, cstage = 0.0;
+    if (mode >= MODE_RK1) {
+        dt = *A.dt;
+        cstage = (mode == MODE_RK1) ? 0.0 : (mode == MODE_RK4 ? 1.0 : 0.5);
+    }
+    if (A.source) {
+        const double t = (A.tdev ? *A.tdev : A.t) + cstage * dt;
+        const int64_t EQ = E * Q3;
+        for (int p = tid; p < Q3; p += nth) {
+            double qs[5];
+            const double* X = G.geo.Xq + e * Q3 + p;
+            mms_source(X[0], X[EQ], X[2 * EQ], t, gamma, qs);
+            const double wj = 1.0 / G.geo.invWJ[e * Q3 + p];
+#pragma unroll
+            for (int s = 0; s < 5; ++s) VA[s * Q3 + p] -= wj * qs[s];
+        }
+    }
+    __syncthreads();
+    // 3. chi^T along z, y, x (VA -> VB -> VA -> VB), face residuals onto the end slabs
+    lds_pass<Q, Q, Q, 2, N, true>(VA, VB, mchi, 5);
+    __syncthreads();
+    lds_pass<Q, Q, N, 1, N, true>(VB, VA, mchi, 5);
+    __syncthreads();
+    lds_pass<Q, N, N, 0, N, true>(VA, VB, mchi, 5);
+    __syncthreads();
+    for (int it = tid; it < 5 * N3; it += nth) {
+        const int s = it / N3, nd = it - s * N3;
+        const int a = nd % N, b = (nd / N) % N, c = nd / N2;
+        double acc = VB[it];
+        const int crd[3] = {a, b, c};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int u1 = d == 0 ? b : a, u2 = d == 2 ? b : c;
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                if (crd[d] != (side ? N - 1 : 0)) continue;
+                const double* r = RF + ((2 * d + side) * 5 + s) * Q2;
+                double f = 0.0;
+                for (int q2 = 0; q2 < Q; ++q2)
+                    for (int q1 = 0; q1 < Q; ++q1) f = __builtin_fma(mchi[q1 * N + u1] * mchi[q2 * N + u2], r[q1 + Q * q2], f);
+                acc += f;
+            }
+        }
+        VB[it] = acc;
+    }
+    __syncthreads();
+    if (mode == MODE_RESIDUAL) {
+        for (int it = tid; it < 5 * N3; it += nth) {
+            const int s = it / N3, nd = it - s * N3;
+            A.out[s * SE + e * N3 + nd] = VB[it];
+        }
+        return;
+    }
+    // 4. weight-adjusted inverse: Pi~^T (VB -> VA -> VB -> VA), 1 / (W J), Pi~ (VA -> VB -> VA -> VB)
+    lds_pass<N, N, N, 0, Q, true>(VB, VA, mpit, 5);
+    __syncthreads();
+    lds_pass<Q, N, N, 1, Q, true>(VA, VB, mpit, 5);
+    __syncthreads();
+    lds_pass<Q, Q, N, 2, Q, true>(VB, VA, mpit, 5);
+    __syncthreads();
+    for (int it = tid; it < 5 * Q3; it += nth) VA[it] *= G.geo.invWJ[e * Q3 + it % Q3];
+    __syncthreads();
+    lds_pass<Q, Q, Q, 2, N, false>(VA, VB, mpit, 5);
+    __syncthreads();
+    lds_pass<Q, Q, N, 1, N, false>(VB, VA, mpit, 5);
+    __syncthreads();
+    lds_pass<Q, N, N, 0, N, false>(VA, VB, mpit, 5);
+    __syncthreads();
+    // 5. RK combination
+    for (int it = tid; it < 5 * N3; it += nth) {
+        const int s = it / N3, nd = it - s * N3;
+        const int64_t gi = s * SE + e * N3 + nd;
+        const double k = -VB[it];
+        switch (mode) {
+            case MODE_RHS: A.out[gi] = k; break;
+            case MODE_RK1: {
+                const double u = A.Uin[gi];
+                A.acc[gi] = __builtin_fma(dt / 6.0, k, u);
+                A.out[gi] = __builtin_fma(0.5 * dt, k, u);
+            } break;
+            case MODE_RK2:
+                A.acc[gi] = __builtin_fma(dt / 3.0, k, A.acc[gi]);
+                A.out[gi] = __builtin_fma(0.5 * dt, k, A.Un[gi]);
+                break;
+            case MODE_RK3:
+                A.acc[gi] = __builtin_fma(dt / 3.0, k, A.acc[gi]);
+                A.out[gi] = __builtin_fma(dt, k, A.Un[gi]);
+                break;
+            default: A.out[gi] = __builtin_fma(dt / 6.0, k, A.acc[gi]); break;
+        }
+    }
+}
+
+static size_t dg_stage_lds(int p, int q) {
+    const int n = p + 1;
+    return (size_t)(2 * q * n + q * q + 3 * q + 5 * q * q * q + 5 * q * q * n + 30 * q * q) * sizeof(double);
+}
+
+static size_t dg_project_lds(int p, int q) { return (size_t)(2 * q * (p + 1) + 5 * (p + 1) * (p + 1) * (p + 1)) * sizeof(double); }
+
 static size_t gl_stage_lds(int p, int q) {
     const int n = p + 1;
     return (size_t)(2 * q * n + q * q + 3 * q + 11 * q * q * q + 66 * q * q) * sizeof(double);
@@ -536,8 +851,9 @@ static size_t gl_stage_lds(int p, int q) {
 
 static size_t gl_project_lds(int p, int q) { return (size_t)(2 * q * (p + 1) + 10 * q * q * q) * sizeof(double); }
 
-size_t gl_lds_bytes(int p, int q) {
-    const size_t a = gl_stage_lds(p, q), b = gl_project_lds(p, q);
+size_t gl_lds_bytes(bool dg, int p, int q) {
+    const size_t a = dg ? dg_stage_lds(p, q) : gl_stage_lds(p, q);
+    const size_t b = dg ? dg_project_lds(p, q) : gl_project_lds(p, q);
     return a > b ? a : b;
 }
 
@@ -552,56 +868,93 @@ static hipError_t gl_geometry_nq(const GLOps* ops, int64_t E, const double* X, c
 
 template <int N, int Q>
 static hipError_t gl_stage_nq(int variant, const StageArgs& a, const GLArgs& g, hipStream_t s) {
+    static_assert(3 * Q * Q <= GL_BLOCK, "one thread per line");
     const size_t lp = gl_project_lds(N - 1, Q), ls = gl_stage_lds(N - 1, Q);
     const unsigned blocks = (unsigned)a.geo.E;
     const int threads = ((3 * Q * Q + 63) / 64) * 64;
-    gl_project_kernel<N, Q><<<blocks, GL_BLOCK, lp, s>>>(g.ops, a.geo.E, a.Uin, a.gamma, g.vhat, g.ft);
+    gl_project_kernel<N, Q, false><<<blocks, GL_BLOCK, lp, s>>>(g.ops, a.geo.E, a.Uin, a.gamma, g.vhat, g.ft);
     if (variant) gl_stage_kernel<N, Q, 1><<<blocks, threads, ls, s>>>(a, g);
     else gl_stage_kernel<N, Q, 0><<<blocks, threads, ls, s>>>(a, g);
     return hipGetLastError();
 }
 
+template <int N, int Q>
+static hipError_t dg_stage_nq(const StageArgs& a, const GLArgs& g, hipStream_t s) {
+    const size_t lp = dg_project_lds(N - 1, Q), ls = dg_stage_lds(N - 1, Q);
+    const unsigned blocks = (unsigned)a.geo.E;
+    const int threads = ((3 * Q * Q + 63) / 64) * 64;
+    static_assert(3 * Q * Q <= DG_BLOCK, "one thread per line");
+    gl_project_kernel<N, Q, true><<<blocks, GL_BLOCK, lp, s>>>(g.ops, a.geo.E, a.Uin, a.gamma, g.vhat, g.ft);
+    dg_stage_kernel<N, Q><<<blocks, threads, ls, s>>>(a, g);
+    return hipGetLastError();
+}
+
 // configure every kernel of an (N, Q) pair for its dynamic LDS (needed when a
 // workgroup uses more than the default 64 KB)
+static hipError_t set_lds(const void* f, size_t bytes) {
+    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
 template <int N, int Q>
 static hipError_t gl_set_lds() {
-    hipError_t e = hipFuncSetAttribute((const void*)gl_project_kernel<N, Q>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)gl_project_lds(N - 1, Q));
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void*)gl_stage_kernel<N, Q, 0>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)gl_stage_lds(N - 1, Q));
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void*)gl_stage_kernel<N, Q, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)gl_stage_lds(N - 1, Q));
+    hipError_t e = set_lds((const void*)gl_project_kernel<N, Q, false>, gl_project_lds(N - 1, Q));
+    if (e == hipSuccess) e = set_lds((const void*)gl_stage_kernel<N, Q, 0>, gl_stage_lds(N - 1, Q));
+    if (e == hipSuccess) e = set_lds((const void*)gl_stage_kernel<N, Q, 1>, gl_stage_lds(N - 1, Q));
     return e;
 }
 
+template <int N, int Q>
+static hipError_t dg_set_lds() {
+    hipError_t e = set_lds((const void*)gl_project_kernel<N, Q, true>, dg_project_lds(N - 1, Q));
+    if (e == hipSuccess) e = set_lds((const void*)dg_stage_kernel<N, Q>, dg_stage_lds(N - 1, Q));
+    return e;
+}
+
+// (n, q) pairs: NSFR with up to 3 extra points per direction, conservative DG
+// with up to n extra (a rule of 2 (p + 1) points); the geometry serves both
 #define NSFR_GL_TABLE(X)                                                                                     \
     X(3, 3) X(3, 4) X(3, 5) X(3, 6) X(4, 4) X(4, 5) X(4, 6) X(4, 7) X(5, 5) X(5, 6) X(5, 7) X(5, 8) X(6, 6) \
         X(6, 7) X(6, 8) X(6, 9)
+#define NSFR_DG_TABLE(X)                                                                                     \
+    X(3, 3) X(3, 4) X(3, 5) X(3, 6) X(4, 4) X(4, 5) X(4, 6) X(4, 7) X(4, 8) X(5, 5) X(5, 6) X(5, 7) X(5, 8) \
+        X(5, 9) X(5, 10) X(6, 6) X(6, 7) X(6, 8) X(6, 9) X(6, 10) X(6, 11) X(6, 12)
 
 hipError_t launch_gl_geometry(int p, int q, const GLOps* ops, int64_t E, const double* X, const double* Cline,
                               double* Cq, double* Cf, double* invWJ, double* Xq, hipStream_t s) {
 #define NSFR_GEO(NN, QQ) \
     if (p + 1 == NN && q == QQ) return gl_geometry_nq<NN, QQ>(ops, E, X, Cline, Cq, Cf, invWJ, Xq, s);
-    NSFR_GL_TABLE(NSFR_GEO)
+    NSFR_DG_TABLE(NSFR_GEO)
 #undef NSFR_GEO
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_gl_stage(int p, int q, int variant, const StageArgs& a, const GLArgs& g, hipStream_t s) {
+hipError_t launch_gl_stage(bool dg, int p, int q, int variant, const StageArgs& a, const GLArgs& g, hipStream_t s) {
 #define NSFR_STG(NN, QQ) \
     if (p + 1 == NN && q == QQ) return gl_stage_nq<NN, QQ>(variant, a, g, s);
-    NSFR_GL_TABLE(NSFR_STG)
+#define NSFR_DGS(NN, QQ) \
+    if (p + 1 == NN && q == QQ) return dg_stage_nq<NN, QQ>(a, g, s);
+    if (dg) {
+        NSFR_DG_TABLE(NSFR_DGS)
+    } else {
+        NSFR_GL_TABLE(NSFR_STG)
+    }
 #undef NSFR_STG
+#undef NSFR_DGS
     return hipErrorInvalidValue;
 }
 
-hipError_t gl_prepare(int p, int q) {
+hipError_t gl_prepare(bool dg, int p, int q) {
 #define NSFR_LDS(NN, QQ) \
     if (p + 1 == NN && q == QQ) return gl_set_lds<NN, QQ>();
-    NSFR_GL_TABLE(NSFR_LDS)
+#define NSFR_DGL(NN, QQ) \
+    if (p + 1 == NN && q == QQ) return dg_set_lds<NN, QQ>();
+    if (dg) {
+        NSFR_DG_TABLE(NSFR_DGL)
+    } else {
+        NSFR_GL_TABLE(NSFR_LDS)
+    }
 #undef NSFR_LDS
+#undef NSFR_DGL
     return hipErrorInvalidValue;
 }
 

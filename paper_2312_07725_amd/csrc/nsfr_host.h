@@ -21,8 +21,8 @@ struct HostOps {
 void build_ops(int p, double c, Ops& ops, HostOps& h);
 
 // ---- uncollocated (Gauss-Legendre) quadrature
-constexpr int MAXQ = 9;   // n + overintegration, at most 6 + 3
-constexpr int MAX_OVERINT = 3;
+constexpr int MAXQ = 12;          // n + overintegration: NSFR up to n + 3, conservative DG up to 2 n
+constexpr int MAX_OVERINT = 3;    // NSFR
 
 // 1D operators of the Gauss-Legendre variant (row-major; n solution nodes on
 // LGL, q quadrature points), copied to device memory once per context.
@@ -35,6 +35,7 @@ struct GLOps {
     double pit[MAXN * MAXQ];    // n x q: ESFR projection (M + K)^-1 chi^T Wq (Eq. Fr projection)
     double sqh[MAXQ * MAXQ];    // q x q: (Wq Dq - Dq^T Wq) / 2, exactly antisymmetric
     double tl[MAXQ], tr[MAXQ];  // flux basis (Lagrange on the quadrature points) at -1, +1
+    double dq[MAXQ * MAXQ];     // q x q: derivative of the flux basis at the quadrature points
 };
 
 void build_gl_ops(int p, int q, double c, const HostOps& h, GLOps& g);
@@ -129,11 +130,13 @@ hipError_t launch_ensemble_stage(const StageArgs* table, const int2* items, int 
                                  size_t lds_bytes, int grid, hipStream_t s);
 
 // Gauss-Legendre variant (gl.hip): p = 2..5 with q = p + 1 .. p + 4 points
+// (NSFR) or q = p + 1 .. 2 (p + 1) points (conservative DG, dg = true)
 hipError_t launch_gl_geometry(int p, int q, const GLOps* ops, int64_t E, const double* X, const double* Cline,
                               double* Cq, double* Cf, double* invWJ, double* Xq, hipStream_t s);
-// the projection kernel, then the stage kernel (one element per workgroup)
-hipError_t launch_gl_stage(int p, int q, int variant, const StageArgs& a, const GLArgs& g, hipStream_t s);
-size_t gl_lds_bytes(int p, int q);   // dynamic LDS of the larger of the two kernels
-hipError_t gl_prepare(int p, int q);  // allow that much dynamic LDS on the current device
+// the projection (NSFR) or face-trace (DG) kernel, then the stage kernel
+// (one element per workgroup)
+hipError_t launch_gl_stage(bool dg, int p, int q, int variant, const StageArgs& a, const GLArgs& g, hipStream_t s);
+size_t gl_lds_bytes(bool dg, int p, int q);   // dynamic LDS of the larger of the two kernels
+hipError_t gl_prepare(bool dg, int p, int q);  // allow that much dynamic LDS on the current device
 
 }  // namespace nsfr

@@ -236,9 +236,17 @@ void build_gl_ops(int p, int q, double c, const HostOps& h, GLOps& g) {
         for (int k = 0; k < n * q; ++k) out[k] = R[k];
     }
     // flux basis: differentiation on the quadrature points and end values
-    double Dq[MAXQ * MAXQ];
-    for (int i = 0; i < q; ++i)
-        for (int j = 0; j < q; ++j) Dq[i * q + j] = lagrange_d(g.xq, q, j, g.xq[i]);
+    // (diagonal = minus the off-diagonal row sum, so that Dq 1 = 0 to rounding)
+    double* Dq = g.dq;
+    for (int i = 0; i < q; ++i) {
+        double rs = 0.0;
+        for (int j = 0; j < q; ++j)
+            if (j != i) {
+                Dq[i * q + j] = lagrange_d(g.xq, q, j, g.xq[i]);
+                rs += Dq[i * q + j];
+            }
+        Dq[i * q + i] = -rs;
+    }
     for (int i = 0; i < q; ++i) {
         g.sqh[i * q + i] = 0.0;
         for (int j = i + 1; j < q; ++j) {

@@ -67,15 +67,20 @@ def test_null_arguments(L):
 
 
 def test_config_layout_matches_header():
-    # int32 p, int32 ne[3], 6 doubles, 6 int32 = 88 bytes, doubles 8-aligned
-    assert ctypes.sizeof(nsfr.Config) == 88
+    # int32 p, int32 ne[3], 6 doubles, 7 int32 = 92 bytes, padded to 96 (doubles 8-aligned)
+    assert ctypes.sizeof(nsfr.Config) == 96
     assert nsfr.Config.lo.offset == 16
     assert nsfr.Config.flux.offset == 64
     assert nsfr.Config.quad.offset == 80 and nsfr.Config.overint.offset == 84
+    assert nsfr.Config.scheme.offset == 88
 
 
-def test_create_rejects_tile_with_gl_rule(L):
-    cfg = nsfr.make_config(3, 2, quad=1, tile=2)
+@pytest.mark.parametrize("kw", [dict(quad=1, tile=2), dict(scheme=2, quad=1), dict(scheme=1, quad=0),
+                                dict(scheme=1, quad=1, diss=1), dict(scheme=1, quad=1, overint=5),
+                                dict(scheme=0, quad=1, overint=4)])
+def test_create_rejects_invalid_quadrature_or_scheme(L, kw):
+    cfg = nsfr.make_config(3, 2, **kw)
     ctx = ctypes.c_void_p()
     assert L.nsfr_create(ctypes.byref(cfg), None, ctypes.byref(ctx)) == nsfr.NSFR_EINVAL
     assert not ctx.value
+    assert L.nsfr_last_error()
