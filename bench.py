@@ -101,8 +101,8 @@ def per_launch(fn, reps, stream):
     return [ev[i].elapsed_time(ev[i + 1]) / 1e3 for i in range(reps)]
 
 
-def rhs_stats(nsfr, inputs, p, ne, c, reps=200, warm=20, quad="lgl", overint=0):
-    g = nsfr.NSFR(p, ne, beta=0.2, c=c, quad=quad, overint=overint)
+def rhs_stats(nsfr, inputs, p, ne, c, reps=200, warm=20, quad="lgl", overint=0, scheme="nsfr"):
+    g = nsfr.NSFR(p, ne, beta=0.2, c=c, quad=quad, overint=overint, scheme=scheme)
     U = inputs.tgv_state(g.node_coords().cpu()).cuda().contiguous()
     out = g.empty()
     st = torch.cuda.current_stream()
@@ -303,6 +303,20 @@ def main():
             r["vs_lgl_same_p"] = r["rhs_median_us"] / extra["rhs_16cubed"][f"p{pp}"]["rhs_median_us"]
             extra["rhs_16cubed_gl"][f"p{pp}_q{pp + 1 + ov}"] = r
             del gg, UU
+        # the paper's cost comparison (Sec. 7.4) on these kernels: NSFR-EC with
+        # c_DG, conservative DG (Roe) and DG overintegrated to 2 (p + 1) points,
+        # all on the Gauss-Legendre rule, warped TGV, one rhs
+        extra["scheme_cost_gl"] = {}
+        for ne_ in (8, 16):
+            for pp in (3, 4, 5):
+                t = {}
+                for name, sch, ov in (("nsfr", "nsfr", 0), ("dg", "dg", 0), ("dg_overint", "dg", pp + 1)):
+                    gg, UU, r = rhs_stats(nsfr, inputs, pp, ne_, 0.0, reps=50, warm=5, quad="gl", overint=ov,
+                                          scheme=sch)
+                    t[name] = r["rhs_median_us"]
+                    del gg, UU
+                extra["scheme_cost_gl"][f"ne{ne_}_p{pp}"] = {
+                    "rhs_us": t, "nsfr_over_dg": t["nsfr"] / t["dg"], "dg_overint_over_nsfr": t["dg_overint"] / t["nsfr"]}
         extra["rhs_32cubed"] = {}   # working sets of 0.3-1.1 GB: beyond the 256 MB last-level cache
         for pp in (3, 4, 5):
             gg, UU, r = rhs_stats(nsfr, inputs, pp, 32, nsfr.c_hu(pp), reps=200, warm=10)

@@ -78,7 +78,7 @@ static nsfr_status validate(const nsfr_config* c) {
     if (c->flux < 0 || c->flux > 1) return bad("flux must be 0 or 1");
     if (c->surface_diss < 0 || c->surface_diss > 2) return bad("surface_diss must be 0, 1 or 2");
     if (c->source < 0 || c->source > 1) return bad("source must be 0 or 1");
-    if (c->tile < 0 || c->tile > max_epb(c->p)) return bad("tile out of range for this p");
+    if (c->tile < 0 || (c->quad == 0 && c->tile > max_epb(c->p))) return bad("tile out of range for this p");
     if (c->quad < 0 || c->quad > 1) return bad("quad must be 0 (LGL collocated) or 1 (Gauss-Legendre)");
     if (c->scheme < 0 || c->scheme > 1) return bad("scheme must be 0 (NSFR) or 1 (conservative DG)");
     if (c->scheme == 1 && c->quad != 1) return bad("conservative DG runs on the Gauss-Legendre rule (quad = 1)");
@@ -88,7 +88,8 @@ static nsfr_status validate(const nsfr_config* c) {
     if (c->overint < 0 || c->overint > omax)
         return bad("overint must be in 0.." + std::to_string(omax) + (c->scheme == 1 ? " for DG" : " for NSFR"));
     if (c->quad == 0 && c->overint != 0) return bad("overintegration needs the Gauss-Legendre rule (quad = 1)");
-    if (c->quad == 1 && c->tile != 0) return bad("the Gauss-Legendre kernels take no tile (tile must be 0)");
+    if (c->quad == 1 && c->scheme == 0 && c->tile > 1)
+        return bad("the NSFR Gauss-Legendre kernel runs one element per workgroup (tile must be 0 or 1)");
     return NSFR_OK;
 }
 
@@ -204,16 +205,23 @@ static nsfr_status gl_setup(nsfr_ctx* c) {
     const int q = c->n + c->cfg.overint;
     c->q = q;
     const bool dg = c->cfg.scheme == 1;
-    const size_t need = gl_lds_bytes(dg, c->p, q);
     int lds_max = 0;
     HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, c->dev));
+    const int emax = gl_max_epb(dg, c->p, q, (size_t)lds_max);
+    if (c->cfg.tile > emax && emax > 0) {
+        set_error("tile " + std::to_string(c->cfg.tile) + " exceeds the " + std::to_string(emax) +
+                  " elements per workgroup that fit this device for this p and rule");
+        return NSFR_EINVAL;
+    }
+    c->epb = c->cfg.tile ? c->cfg.tile : gl_default_epb(dg, c->p, q, c->E);
+    const size_t need = gl_lds_bytes(dg, c->p, q, c->epb);
     if (need > (size_t)lds_max) {
         set_error(std::string(dg ? "DG" : "NSFR") + " Gauss-Legendre kernels for p = " + std::to_string(c->p) + ", " + std::to_string(q) +
                   " points need " + std::to_string(need) + " bytes of LDS per workgroup; the device allows " +
                   std::to_string(lds_max));
         return NSFR_ENOTSUP;
     }
-    HIP_TRY(gl_prepare(dg, c->p, q));
+    HIP_TRY(gl_prepare(dg, c->p, q, need));
     GLOps h;
     build_gl_ops(c->p, q, c->cfg.c_fr, c->hops, h);
     const size_t E = (size_t)c->E, q2 = (size_t)q * q, q3 = q2 * q;

@@ -41,24 +41,82 @@ constexpr int GL_BLOCK = 256;   // projection kernels; NSFR stage (3 q^2 <= 243 
 constexpr int DG_BLOCK = 512;   // DG stage (3 q^2 <= 432 line threads at q = 12)
 
 // ---- sum-factorised 1D operator in LDS: dst = M applied along axis AX of
-// src (dims S0 x S1 x S2, x fastest) for `ns` states; M is OUT x IN
-// row-major, or its transpose stored IN x OUT when TR.
+// src (dims S0 x S1 x S2, x fastest) for `ns` contiguous blocks; M is
+// OUT x IN row-major, or its transpose stored IN x OUT when TR. One thread
+// per (block, line): the line's IN inputs are read once into registers and
+// its OUT outputs written once, so the index arithmetic is paid per line.
 template <int S0, int S1, int S2, int AX, int OUT, bool TR>
 __device__ __forceinline__ void lds_pass(const double* __restrict__ src, double* __restrict__ dst,
                                          const double* __restrict__ M, int ns) {
     constexpr int IN = AX == 0 ? S0 : (AX == 1 ? S1 : S2);
-    constexpr int D0 = AX == 0 ? OUT : S0, D1 = AX == 1 ? OUT : S1, D2 = AX == 2 ? OUT : S2;
-    constexpr int SRC = S0 * S1 * S2, DST = D0 * D1 * D2;
-    constexpr int ST = AX == 0 ? 1 : (AX == 1 ? S0 : S0 * S1);
-    for (int it = threadIdx.x; it < ns * DST; it += blockDim.x) {
-        const int s = it / DST, r = it - s * DST;
-        const int i0 = r % D0, i1 = (r / D0) % D1, i2 = r / (D0 * D1);
-        const int o = AX == 0 ? i0 : (AX == 1 ? i1 : i2);
-        const double* x = src + s * SRC + (AX == 0 ? 0 : i0) + S0 * ((AX == 1 ? 0 : i1) + S1 * (AX == 2 ? 0 : i2));
-        double acc = 0.0;
+    constexpr int D0 = AX == 0 ? OUT : S0;
+    constexpr int SRC = S0 * S1 * S2, NL = SRC / IN, DST = NL * OUT;
+    constexpr int SST = AX == 0 ? 1 : (AX == 1 ? S0 : S0 * S1);   // stride along the axis in src
+    constexpr int DSS = AX == 0 ? 1 : (AX == 1 ? D0 : S0 * S1);   // and in dst
+    for (int it = threadIdx.x; it < ns * NL; it += blockDim.x) {
+        const int b = it / NL, ln = it - b * NL;
+        int sb, db;
+        if (AX == 0) {          // ln = i1 + S1 i2
+            sb = ln * S0;
+            db = ln * OUT;
+        } else if (AX == 1) {   // ln = i0 + S0 i2
+            const int i0 = ln % S0, i2 = ln / S0;
+            sb = i0 + S0 * S1 * i2;
+            db = i0 + S0 * OUT * i2;
+        } else {                // ln = i0 + S0 i1
+            sb = ln;
+            db = ln;
+        }
+        const double* x = src + b * SRC + sb;
+        double v[IN];
 #pragma unroll
-        for (int m = 0; m < IN; ++m) acc = __builtin_fma(TR ? M[m * OUT + o] : M[o * IN + m], x[m * ST], acc);
-        dst[s * DST + r] = acc;
+        for (int m = 0; m < IN; ++m) v[m] = x[m * SST];
+        double* y = dst + b * DST + db;
+#pragma unroll
+        for (int o = 0; o < OUT; ++o) {
+            double acc = 0.0;
+#pragma unroll
+            for (int m = 0; m < IN; ++m) acc = __builtin_fma(TR ? M[m * OUT + o] : M[o * IN + m], v[m], acc);
+            y[o * DSS] = acc;
+        }
+    }
+}
+
+// Face slabs of a coefficient array X [nb][5][n^3] (nb element blocks): copy
+// the six end slabs into SL [nb][6][5][n^2] (tangential indices in increasing
+// direction order, first fastest).
+template <int N>
+__device__ __forceinline__ void gather_slabs(const double* __restrict__ X, double* __restrict__ SL, int nb) {
+    constexpr int N2 = N * N, N3 = N2 * N;
+    for (int it = threadIdx.x; it < nb * 30 * N2; it += blockDim.x) {
+        const int el = it / (30 * N2), r = it - el * 30 * N2;
+        const int f = r / (5 * N2), r2 = r - f * 5 * N2;
+        const int s = r2 / N2, t = r2 - s * N2;
+        const int d = f / 2, end = (f % 2) ? N - 1 : 0;
+        const int u1 = t % N, u2 = t / N;
+        const int nd = d == 0 ? end + N * u1 + N2 * u2 : (d == 1 ? u1 + N * end + N2 * u2 : u1 + N * u2 + N2 * end);
+        SL[it] = X[(el * 5 + s) * N3 + nd];
+    }
+}
+
+// Add the six face slabs FS [nb][6][5][n^2] onto the coefficient array X
+// [nb][5][n^3] (node-parallel: each node adds the slabs of the faces it lies on).
+template <int N>
+__device__ __forceinline__ void scatter_add_slabs(double* __restrict__ X, const double* __restrict__ FS, int nb) {
+    constexpr int N2 = N * N, N3 = N2 * N;
+    for (int it = threadIdx.x; it < nb * 5 * N3; it += blockDim.x) {
+        const int el = it / (5 * N3), r = it - el * 5 * N3;
+        const int s = r / N3, nd = r - s * N3;
+        const int a = nd % N, b = (nd / N) % N, c = nd / N2;
+        const double* fs = FS + el * 30 * N2 + s * N2;
+        double acc = X[it];
+        if (a == 0) acc += fs[0 * 5 * N2 + b + N * c];
+        if (a == N - 1) acc += fs[1 * 5 * N2 + b + N * c];
+        if (b == 0) acc += fs[2 * 5 * N2 + a + N * c];
+        if (b == N - 1) acc += fs[3 * 5 * N2 + a + N * c];
+        if (c == 0) acc += fs[4 * 5 * N2 + a + N * b];
+        if (c == N - 1) acc += fs[5 * 5 * N2 + a + N * b];
+        X[it] = acc;
     }
 }
 
@@ -185,10 +243,14 @@ __global__ __launch_bounds__(GL_BLOCK) void gl_project_kernel(const GLOps* __res
                                                               double* vhat, double* ft) {
     constexpr int N2 = N * N, N3 = N2 * N, Q2 = Q * Q, Q3 = Q2 * Q;
     extern __shared__ double lds[];
+    constexpr int AS = DG ? 5 * N3 : 5 * Q3, BS = DG ? 0 : 5 * Q3;
     double* mchi = lds;              // Q x N
     double* mpi = mchi + Q * N;      // N x Q
-    double* A = mpi + N * Q;         // 5 Q^3 (DG: 5 N^3)
-    double* B = A + 5 * Q3;          // 5 Q^3 (not used by DG)
+    double* A = mpi + N * Q;         // AS
+    double* B = A + AS;              // BS
+    double* SL = B + BS;             // [6][5][N^2] end slabs
+    double* T = SL + 30 * N2;        // [6][5][Q N]
+    double* SF = T + 30 * Q * N;     // [6][5][Q^2]
     const int tid = threadIdx.x;
     const int64_t e = blockIdx.x;
     const int64_t SE = E * N3;
@@ -229,22 +291,17 @@ __global__ __launch_bounds__(GL_BLOCK) void gl_project_kernel(const GLOps* __res
             vhat[s * SE + e * N3 + nd] = A[i];
         }
     }
-    // v^ (DG: u) at the face points: the end slab of the coefficients, interpolated in
-    // the two tangential directions
-    for (int it = tid; it < 6 * 5 * Q2; it += blockDim.x) {
-        const int f = it / (5 * Q2), r = it - f * 5 * Q2;
-        const int s = r / Q2, t = r - s * Q2;
-        const int d = f / 2, end = (f % 2) ? N - 1 : 0;
-        const int t1 = t % Q, t2 = t / Q;
-        double acc = 0.0;
-#pragma unroll
-        for (int c = 0; c < N; ++c)
-#pragma unroll
-            for (int b = 0; b < N; ++b) {
-                const int nd = d == 0 ? end + N * b + N2 * c : (d == 1 ? b + N * end + N2 * c : b + N * c + N2 * end);
-                acc = __builtin_fma(mchi[t1 * N + b] * mchi[t2 * N + c], A[s * N3 + nd], acc);
-            }
-        ft[((int64_t)(f * 5 + s) * E + e) * Q2 + t] = acc;
+    // v^ (DG: u) at the face points: the end slab of the coefficients,
+    // interpolated along the first and then the second tangential direction
+    gather_slabs<N>(A, SL, 1);
+    __syncthreads();
+    lds_pass<N, N, 1, 0, Q, false>(SL, T, mchi, 30);
+    __syncthreads();
+    lds_pass<Q, N, 1, 1, Q, false>(T, SF, mchi, 30);
+    __syncthreads();
+    for (int it = tid; it < 30 * Q2; it += blockDim.x) {
+        const int fs = it / Q2, t = it - fs * Q2;
+        ft[((int64_t)fs * E + e) * Q2 + t] = SF[it];
     }
 }
 
@@ -263,6 +320,7 @@ __global__ __launch_bounds__(GL_BLOCK) void gl_stage_kernel(StageArgs A, GLArgs 
     double* BB = BA + 6 * Q3;         // 5 Q^3: pass buffer, then the volume residual
     double* FP = BB + 5 * Q3;         // [6 faces][6][Q^2]: primitives at the own face points
     double* RF = FP + 36 * Q2;        // [6 faces][5][Q^2]: face-point residuals
+    double* TF = RF + 30 * Q2;        // [6 faces][5][Q N]: their first tangential contraction
     const int tid = threadIdx.x, nth = blockDim.x;
     const int64_t e = blockIdx.x;
     const int64_t E = A.geo.E;
@@ -467,32 +525,17 @@ __global__ __launch_bounds__(GL_BLOCK) void gl_stage_kernel(StageArgs A, GLArgs 
 
     // 3. to the coefficients: chi^T along z, y, x of the volume residual, then
     //    the face residuals through the tangential chi^T onto the end slabs
+    //    (the face residuals go through the tangential chi^T, RF -> TF -> RF as
+    //    [6][5][N^2], alongside the first two volume passes)
     lds_pass<Q, Q, Q, 2, N, true>(BB, BA, mchi, 5);
+    lds_pass<Q, Q, 1, 0, N, true>(RF, TF, mchi, 30);
     __syncthreads();
     lds_pass<Q, Q, N, 1, N, true>(BA, BB, mchi, 5);
+    lds_pass<N, Q, 1, 1, N, true>(TF, RF, mchi, 30);
     __syncthreads();
     lds_pass<Q, N, N, 0, N, true>(BB, BA, mchi, 5);
     __syncthreads();
-    for (int it = tid; it < 5 * N3; it += nth) {
-        const int s = it / N3, nd = it - s * N3;
-        const int a = nd % N, b = (nd / N) % N, c = nd / N2;
-        double acc = BA[it];
-        const int crd[3] = {a, b, c};
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const int u1 = d == 0 ? b : a, u2 = d == 2 ? b : c;   // tangential coefficient indices
-#pragma unroll
-            for (int side = 0; side < 2; ++side) {
-                if (crd[d] != (side ? N - 1 : 0)) continue;
-                const double* r = RF + ((2 * d + side) * 5 + s) * Q2;
-                double f = 0.0;
-                for (int q2 = 0; q2 < Q; ++q2)
-                    for (int q1 = 0; q1 < Q; ++q1) f = __builtin_fma(mchi[q1 * N + u1] * mchi[q2 * N + u2], r[q1 + Q * q2], f);
-                acc += f;
-            }
-        }
-        BA[it] = acc;
-    }
+    scatter_add_slabs<N>(BA, RF, 1);
     __syncthreads();
     if (mode == MODE_RESIDUAL) {
         for (int it = tid; it < 5 * N3; it += nth) {
@@ -614,25 +657,30 @@ __device__ __forceinline__ void roe_flux_dev(const double A[5], const double B[5
     for (int s = 0; s < 5; ++s) F[s] -= k * D[s];
 }
 
-// One element per workgroup. LDS: the 1D operators, VA [5][q^3] (states at
-// the volume points, then the volume residual, then ping-pong), VB [5][q^2 n]
-// (ping-pong), RF [6][5][q^2] (face-point residuals).
+// epb elements per workgroup (A.epb), one thread per (element, line). LDS:
+// the 1D operators, VA [epb][5][q^3] (states at the volume points, then the
+// volume residual, then ping-pong), VB [epb][5][q^2 n] (ping-pong), RF
+// [epb][6][5][q^2] (face-point residuals). Every sum-factorised pass treats the
+// epb x 5 state blocks of a buffer as one contiguous array.
 template <int N, int Q>
 __global__ __launch_bounds__(DG_BLOCK) void dg_stage_kernel(StageArgs A, GLArgs G) {
-    constexpr int N2 = N * N, N3 = N2 * N, Q2 = Q * Q, Q3 = Q2 * Q;
+    constexpr int N2 = N * N, N3 = N2 * N, Q2 = Q * Q, Q3 = Q2 * Q, L3 = 3 * Q2;
     extern __shared__ double lds[];
+    const int epb = A.epb;
     double* mchi = lds;               // Q x N
     double* mpit = mchi + Q * N;      // N x Q
     double* mdq = mpit + N * Q;       // Q x Q
     double* mtl = mdq + Q2;           // Q
     double* mtr = mtl + Q;            // Q
     double* mw = mtr + Q;             // Q
-    double* VA = mw + Q;              // 5 Q^3
-    double* VB = VA + 5 * Q3;         // 5 Q^2 N
-    double* RF = VB + 5 * Q2 * N;     // [6][5][Q^2]
+    double* VA = mw + Q;              // epb 5 Q^3
+    double* VB = VA + epb * 5 * Q3;   // epb 5 Q^2 N
+    double* RF = VB + epb * 5 * Q2 * N;   // epb [6][5][Q^2]
+    double* TF = RF + epb * 30 * Q2;      // epb [6][5][Q N]
     const int tid = threadIdx.x, nth = blockDim.x;
-    const int64_t e = blockIdx.x;
     const int64_t E = A.geo.E;
+    const int64_t e0 = (int64_t)blockIdx.x * epb;
+    const int nel = (int)(E - e0 < epb ? E - e0 : epb);   // elements of this block that exist
     const int64_t SE = E * N3;
     const double gamma = A.gamma, gm1 = gamma - 1.0;
     const double pref = reference_pressure(A.Uin, SE, gm1);
@@ -647,29 +695,35 @@ __global__ __launch_bounds__(DG_BLOCK) void dg_stage_kernel(StageArgs A, GLArgs 
         mtr[i] = ops->tr[i];
         mw[i] = ops->wq[i];
     }
-    // 1. u at the volume points: chi along x, y, z (VB -> VA -> VB -> VA)
-    for (int i = tid; i < 5 * N3; i += nth) {
-        const int s = i / N3, nd = i - s * N3;
-        VB[i] = A.Uin[s * SE + e * N3 + nd];
+    // 1. u at the volume points: chi along x, y, z (VB -> VA -> VB -> VA);
+    //    missing elements of a ragged last block are zero-filled
+    for (int i = tid; i < epb * 5 * N3; i += nth) {
+        const int el = i / (5 * N3), r = i - el * 5 * N3;
+        const int s = r / N3, nd = r - s * N3;
+        VB[i] = el < nel ? A.Uin[s * SE + (e0 + el) * N3 + nd] : 0.0;
     }
     __syncthreads();
-    lds_pass<N, N, N, 0, Q, false>(VB, VA, mchi, 5);
+    lds_pass<N, N, N, 0, Q, false>(VB, VA, mchi, 5 * epb);
     __syncthreads();
-    lds_pass<Q, N, N, 1, Q, false>(VA, VB, mchi, 5);
+    lds_pass<Q, N, N, 1, Q, false>(VA, VB, mchi, 5 * epb);
     __syncthreads();
-    lds_pass<Q, Q, N, 2, Q, false>(VB, VA, mchi, 5);
+    lds_pass<Q, Q, N, 2, Q, false>(VB, VA, mchi, 5 * epb);
     __syncthreads();
 
-    // 2. one thread per line: the contravariant flux f^r_k at the line's points,
-    //    its flux-basis derivative (R_v[a] = w_a W_perp sum_b Dq[a][b] f^r_k(b)),
-    //    its values at the two ends, and Roe's flux with the neighbour there
-    const int lt = tid;
-    const bool active = lt < 3 * Q2;
-    const int dir = active ? lt / Q2 : 0;
-    const int l = active ? lt - dir * Q2 : 0;
+    // 2. one thread per (element, line): the contravariant flux f^r_k at the
+    //    line's points, its flux-basis derivative (R_v[a] = w_a W_perp
+    //    sum_b Dq[a][b] f^r_k(b)), its values at the two ends, and Roe's flux
+    //    with the neighbour there
+    const int el = tid / L3;
+    const bool active = el < nel;
+    const int lt = active ? tid - el * L3 : 0;
+    const int dir = lt / Q2;
+    const int l = lt - dir * Q2;
+    const int64_t e = e0 + (active ? el : 0);
     const int t1 = l % Q, t2 = l / Q;
     const int base = dir == 0 ? Q * t1 + Q2 * t2 : (dir == 1 ? t1 + Q2 * t2 : t1 + Q * t2);
     const int stride = dir == 0 ? 1 : (dir == 1 ? Q : Q2);
+    double* va = VA + (active ? el : 0) * 5 * Q3;
     double Rv[5][Q], Rf[2][5];
 #pragma unroll
     for (int s = 0; s < 5; ++s) {
@@ -680,16 +734,36 @@ __global__ __launch_bounds__(DG_BLOCK) void dg_stage_kernel(StageArgs A, GLArgs 
     if (active) {
         const double* Cl = G.geo.Cq + (int64_t)(3 * dir) * E * Q3 + e * Q3 + l;
         const int64_t CS = E * Q3;
+        const int64_t FS = E * Q2;
+        // face operands first: their latency overlaps the volume work
+        double uo[2][5], un[2][5], nxs[2], nys[2], nzs[2];
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const int f = 2 * dir + side;
+            const double sg = side ? 1.0 : -1.0;
+            const double* Cfo = G.geo.Cf + ((int64_t)(f * 3) * E + e) * Q2 + l;
+            const int en = A.geo.nbr[(int64_t)f * E + e];
+            const int fn = 2 * dir + (1 - side);
+            const double* Cfn = G.geo.Cf + ((int64_t)(fn * 3) * E + en) * Q2 + l;
+            nxs[side] = 0.5 * sg * (Cfo[0] + Cfn[0]);
+            nys[side] = 0.5 * sg * (Cfo[FS] + Cfn[FS]);
+            nzs[side] = 0.5 * sg * (Cfo[2 * FS] + Cfn[2 * FS]);
+#pragma unroll
+            for (int s = 0; s < 5; ++s) {
+                uo[side][s] = G.ft[((int64_t)(f * 5 + s) * E + e) * Q2 + l];
+                un[side][s] = G.ft[((int64_t)(fn * 5 + s) * E + en) * Q2 + l];
+            }
+        }
 #pragma unroll
         for (int b = 0; b < Q; ++b) {
             const int t = base + b * stride;
-            const double r = VA[t], m1 = VA[Q3 + t], m2 = VA[2 * Q3 + t], m3 = VA[3 * Q3 + t], en = VA[4 * Q3 + t];
+            const double r = va[t], m1 = va[Q3 + t], m2 = va[2 * Q3 + t], m3 = va[3 * Q3 + t], en = va[4 * Q3 + t];
             const double cx = Cl[b * Q2], cy = Cl[CS + b * Q2], cz = Cl[2 * CS + b * Q2];
             const double ir = 1.0 / r;
-            const double un = (m1 * cx + m2 * cy + m3 * cz) * ir;
+            const double unb = (m1 * cx + m2 * cy + m3 * cz) * ir;
             const double p = gm1 * (en - 0.5 * (m1 * m1 + m2 * m2 + m3 * m3) * ir);
             const double pd = p - pref;
-            const double fr[5] = {r * un, m1 * un + pd * cx, m2 * un + pd * cy, m3 * un + pd * cz, (en + p) * un};
+            const double fr[5] = {r * unb, m1 * unb + pd * cx, m2 * unb + pd * cy, m3 * unb + pd * cz, (en + p) * unb};
 #pragma unroll
             for (int s = 0; s < 5; ++s) {
 #pragma unroll
@@ -701,22 +775,9 @@ __global__ __launch_bounds__(DG_BLOCK) void dg_stage_kernel(StageArgs A, GLArgs 
         // face terms: N . f* - s t . f^r (s = -1 at the left end, +1 at the right)
 #pragma unroll
         for (int side = 0; side < 2; ++side) {
-            const int f = 2 * dir + side;
             const double sg = side ? 1.0 : -1.0;
-            const int64_t FS = E * Q2;
-            const double* Cfo = G.geo.Cf + ((int64_t)(f * 3) * E + e) * Q2 + l;
-            const int en = A.geo.nbr[(int64_t)f * E + e];
-            const int fn = 2 * dir + (1 - side);
-            const double* Cfn = G.geo.Cf + ((int64_t)(fn * 3) * E + en) * Q2 + l;
-            const double nx = 0.5 * sg * (Cfo[0] + Cfn[0]), ny = 0.5 * sg * (Cfo[FS] + Cfn[FS]),
-                         nz = 0.5 * sg * (Cfo[2 * FS] + Cfn[2 * FS]);
-            double uo[5], un[5], F[5];
-#pragma unroll
-            for (int s = 0; s < 5; ++s) {
-                uo[s] = G.ft[((int64_t)(f * 5 + s) * E + e) * Q2 + l];
-                un[s] = G.ft[((int64_t)(fn * 5 + s) * E + en) * Q2 + l];
-            }
-            roe_flux_dev(uo, un, nx, ny, nz, gamma, pref, F);
+            double F[5];
+            roe_flux_dev(uo[side], un[side], nxs[side], nys[side], nzs[side], gamma, pref, F);
 #pragma unroll
             for (int s = 0; s < 5; ++s) Rf[side][s] = F[s] - sg * Rf[side][s];
         }
@@ -730,7 +791,7 @@ __global__ __launch_bounds__(DG_BLOCK) void dg_stage_kernel(StageArgs A, GLArgs 
 #pragma unroll
                 for (int a = 0; a < Q; ++a) {
                     const double v = Rv[s][a] * (mw[a] * wperp);
-                    double* x = VA + s * Q3 + base + a * stride;
+                    double* x = va + s * Q3 + base + a * stride;
                     if (ph == 0) *x = v;
                     else *x += v;
                 }
@@ -738,10 +799,11 @@ __global__ __launch_bounds__(DG_BLOCK) void dg_stage_kernel(StageArgs A, GLArgs 
         __syncthreads();
     }
     if (active) {
+        double* rf = RF + el * 30 * Q2;
 #pragma unroll
         for (int side = 0; side < 2; ++side)
 #pragma unroll
-            for (int s = 0; s < 5; ++s) RF[((2 * dir + side) * 5 + s) * Q2 + l] = Rf[side][s] * wperp;
+            for (int s = 0; s < 5; ++s) rf[((2 * dir + side) * 5 + s) * Q2 + l] = Rf[side][s] * wperp;
     }
     const int mode = A.mode;
     double dt = 0.0, cstage = 0.0;
@@ -752,70 +814,59 @@ __global__ __launch_bounds__(DG_BLOCK) void dg_stage_kernel(StageArgs A, GLArgs 
     if (A.source) {
         const double t = (A.tdev ? *A.tdev : A.t) + cstage * dt;
         const int64_t EQ = E * Q3;
-        for (int p = tid; p < Q3; p += nth) {
+        for (int i = tid; i < nel * Q3; i += nth) {
+            const int ei = i / Q3, p = i - ei * Q3;
             double qs[5];
-            const double* X = G.geo.Xq + e * Q3 + p;
+            const double* X = G.geo.Xq + (e0 + ei) * Q3 + p;
             mms_source(X[0], X[EQ], X[2 * EQ], t, gamma, qs);
-            const double wj = 1.0 / G.geo.invWJ[e * Q3 + p];
+            const double wj = 1.0 / G.geo.invWJ[(e0 + ei) * Q3 + p];
 #pragma unroll
-            for (int s = 0; s < 5; ++s) VA[s * Q3 + p] -= wj * qs[s];
+            for (int s = 0; s < 5; ++s) VA[(ei * 5 + s) * Q3 + p] -= wj * qs[s];
         }
     }
     __syncthreads();
     // 3. chi^T along z, y, x (VA -> VB -> VA -> VB), face residuals onto the end slabs
-    lds_pass<Q, Q, Q, 2, N, true>(VA, VB, mchi, 5);
+    lds_pass<Q, Q, Q, 2, N, true>(VA, VB, mchi, 5 * epb);
+    lds_pass<Q, Q, 1, 0, N, true>(RF, TF, mchi, 30 * epb);
     __syncthreads();
-    lds_pass<Q, Q, N, 1, N, true>(VB, VA, mchi, 5);
+    lds_pass<Q, Q, N, 1, N, true>(VB, VA, mchi, 5 * epb);
+    lds_pass<N, Q, 1, 1, N, true>(TF, RF, mchi, 30 * epb);
     __syncthreads();
-    lds_pass<Q, N, N, 0, N, true>(VA, VB, mchi, 5);
+    lds_pass<Q, N, N, 0, N, true>(VA, VB, mchi, 5 * epb);
     __syncthreads();
-    for (int it = tid; it < 5 * N3; it += nth) {
-        const int s = it / N3, nd = it - s * N3;
-        const int a = nd % N, b = (nd / N) % N, c = nd / N2;
-        double acc = VB[it];
-        const int crd[3] = {a, b, c};
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const int u1 = d == 0 ? b : a, u2 = d == 2 ? b : c;
-#pragma unroll
-            for (int side = 0; side < 2; ++side) {
-                if (crd[d] != (side ? N - 1 : 0)) continue;
-                const double* r = RF + ((2 * d + side) * 5 + s) * Q2;
-                double f = 0.0;
-                for (int q2 = 0; q2 < Q; ++q2)
-                    for (int q1 = 0; q1 < Q; ++q1) f = __builtin_fma(mchi[q1 * N + u1] * mchi[q2 * N + u2], r[q1 + Q * q2], f);
-                acc += f;
-            }
-        }
-        VB[it] = acc;
-    }
+    scatter_add_slabs<N>(VB, RF, epb);
     __syncthreads();
     if (mode == MODE_RESIDUAL) {
-        for (int it = tid; it < 5 * N3; it += nth) {
-            const int s = it / N3, nd = it - s * N3;
-            A.out[s * SE + e * N3 + nd] = VB[it];
+        for (int it = tid; it < nel * 5 * N3; it += nth) {
+            const int ei = it / (5 * N3), r0 = it - ei * 5 * N3;
+            const int s = r0 / N3, nd = r0 - s * N3;
+            A.out[s * SE + (e0 + ei) * N3 + nd] = VB[it];
         }
         return;
     }
     // 4. weight-adjusted inverse: Pi~^T (VB -> VA -> VB -> VA), 1 / (W J), Pi~ (VA -> VB -> VA -> VB)
-    lds_pass<N, N, N, 0, Q, true>(VB, VA, mpit, 5);
+    lds_pass<N, N, N, 0, Q, true>(VB, VA, mpit, 5 * epb);
     __syncthreads();
-    lds_pass<Q, N, N, 1, Q, true>(VA, VB, mpit, 5);
+    lds_pass<Q, N, N, 1, Q, true>(VA, VB, mpit, 5 * epb);
     __syncthreads();
-    lds_pass<Q, Q, N, 2, Q, true>(VB, VA, mpit, 5);
+    lds_pass<Q, Q, N, 2, Q, true>(VB, VA, mpit, 5 * epb);
     __syncthreads();
-    for (int it = tid; it < 5 * Q3; it += nth) VA[it] *= G.geo.invWJ[e * Q3 + it % Q3];
+    for (int it = tid; it < nel * 5 * Q3; it += nth) {
+        const int ei = it / (5 * Q3), t = it % Q3;
+        VA[it] *= G.geo.invWJ[(e0 + ei) * Q3 + t];
+    }
     __syncthreads();
-    lds_pass<Q, Q, Q, 2, N, false>(VA, VB, mpit, 5);
+    lds_pass<Q, Q, Q, 2, N, false>(VA, VB, mpit, 5 * epb);
     __syncthreads();
-    lds_pass<Q, Q, N, 1, N, false>(VB, VA, mpit, 5);
+    lds_pass<Q, Q, N, 1, N, false>(VB, VA, mpit, 5 * epb);
     __syncthreads();
-    lds_pass<Q, N, N, 0, N, false>(VA, VB, mpit, 5);
+    lds_pass<Q, N, N, 0, N, false>(VA, VB, mpit, 5 * epb);
     __syncthreads();
     // 5. RK combination
-    for (int it = tid; it < 5 * N3; it += nth) {
-        const int s = it / N3, nd = it - s * N3;
-        const int64_t gi = s * SE + e * N3 + nd;
+    for (int it = tid; it < nel * 5 * N3; it += nth) {
+        const int ei = it / (5 * N3), r0 = it - ei * 5 * N3;
+        const int s = r0 / N3, nd = r0 - s * N3;
+        const int64_t gi = s * SE + (e0 + ei) * N3 + nd;
         const double k = -VB[it];
         switch (mode) {
             case MODE_RHS: A.out[gi] = k; break;
@@ -837,24 +888,50 @@ __global__ __launch_bounds__(DG_BLOCK) void dg_stage_kernel(StageArgs A, GLArgs 
     }
 }
 
-static size_t dg_stage_lds(int p, int q) {
+static size_t dg_stage_lds(int p, int q, int epb) {
     const int n = p + 1;
-    return (size_t)(2 * q * n + q * q + 3 * q + 5 * q * q * q + 5 * q * q * n + 30 * q * q) * sizeof(double);
+    return (size_t)(2 * q * n + q * q + 3 * q + epb * (5 * q * q * q + 5 * q * q * n + 30 * q * q + 30 * q * n)) *
+           sizeof(double);
 }
 
-static size_t dg_project_lds(int p, int q) { return (size_t)(2 * q * (p + 1) + 5 * (p + 1) * (p + 1) * (p + 1)) * sizeof(double); }
+// the projection kernels: operators, state buffers, and the face-slab
+// buffers [6][5] x (n^2, q n, q^2)
+static size_t slab_lds(int n, int q) { return (size_t)30 * (n * n + q * n + q * q); }
+
+static size_t dg_project_lds(int p, int q) {
+    const int n = p + 1;
+    return (2 * q * n + 5 * n * n * n + slab_lds(n, q)) * sizeof(double);
+}
 
 static size_t gl_stage_lds(int p, int q) {
     const int n = p + 1;
-    return (size_t)(2 * q * n + q * q + 3 * q + 11 * q * q * q + 66 * q * q) * sizeof(double);
+    return (size_t)(2 * q * n + q * q + 3 * q + 11 * q * q * q + 66 * q * q + 30 * q * n) * sizeof(double);
 }
 
-static size_t gl_project_lds(int p, int q) { return (size_t)(2 * q * (p + 1) + 10 * q * q * q) * sizeof(double); }
+static size_t gl_project_lds(int p, int q) {
+    return (2 * q * (p + 1) + 10 * (size_t)q * q * q + slab_lds(p + 1, q)) * sizeof(double);
+}
 
-size_t gl_lds_bytes(bool dg, int p, int q) {
-    const size_t a = dg ? dg_stage_lds(p, q) : gl_stage_lds(p, q);
+size_t gl_lds_bytes(bool dg, int p, int q, int epb) {
+    const size_t a = dg ? dg_stage_lds(p, q, epb) : gl_stage_lds(p, q);
     const size_t b = dg ? dg_project_lds(p, q) : gl_project_lds(p, q);
     return a > b ? a : b;
+}
+
+int gl_max_epb(bool dg, int p, int q, size_t lds_max) {
+    if (!dg) return 1;
+    int m = DG_BLOCK / (3 * q * q);
+    while (m > 0 && gl_lds_bytes(dg, p, q, m) > lds_max) --m;
+    return m;
+}
+
+int gl_default_epb(bool dg, int p, int q, int64_t E) {
+    if (!dg) return 1;
+    // about 256 threads per workgroup, but at least 2048 workgroups when the
+    // mesh has them (8 per CU)
+    int epb = 256 / (3 * q * q);
+    while (epb > 1 && (E + epb - 1) / epb < 2048) --epb;
+    return epb < 1 ? 1 : epb;
 }
 
 template <int N, int Q>
@@ -880,12 +957,14 @@ static hipError_t gl_stage_nq(int variant, const StageArgs& a, const GLArgs& g, 
 
 template <int N, int Q>
 static hipError_t dg_stage_nq(const StageArgs& a, const GLArgs& g, hipStream_t s) {
-    const size_t lp = dg_project_lds(N - 1, Q), ls = dg_stage_lds(N - 1, Q);
-    const unsigned blocks = (unsigned)a.geo.E;
-    const int threads = ((3 * Q * Q + 63) / 64) * 64;
     static_assert(3 * Q * Q <= DG_BLOCK, "one thread per line");
-    gl_project_kernel<N, Q, true><<<blocks, GL_BLOCK, lp, s>>>(g.ops, a.geo.E, a.Uin, a.gamma, g.vhat, g.ft);
-    dg_stage_kernel<N, Q><<<blocks, threads, ls, s>>>(a, g);
+    const int epb = a.epb;
+    if (epb < 1 || epb * 3 * Q * Q > DG_BLOCK) return hipErrorInvalidConfiguration;
+    const size_t lp = dg_project_lds(N - 1, Q), ls = dg_stage_lds(N - 1, Q, epb);
+    const int threads = ((epb * 3 * Q * Q + 63) / 64) * 64;
+    gl_project_kernel<N, Q, true><<<(unsigned)a.geo.E, GL_BLOCK, lp, s>>>(g.ops, a.geo.E, a.Uin, a.gamma, g.vhat,
+                                                                          g.ft);
+    dg_stage_kernel<N, Q><<<(unsigned)((a.geo.E + epb - 1) / epb), threads, ls, s>>>(a, g);
     return hipGetLastError();
 }
 
@@ -896,17 +975,17 @@ static hipError_t set_lds(const void* f, size_t bytes) {
 }
 
 template <int N, int Q>
-static hipError_t gl_set_lds() {
-    hipError_t e = set_lds((const void*)gl_project_kernel<N, Q, false>, gl_project_lds(N - 1, Q));
-    if (e == hipSuccess) e = set_lds((const void*)gl_stage_kernel<N, Q, 0>, gl_stage_lds(N - 1, Q));
-    if (e == hipSuccess) e = set_lds((const void*)gl_stage_kernel<N, Q, 1>, gl_stage_lds(N - 1, Q));
+static hipError_t gl_set_lds(size_t bytes) {
+    hipError_t e = set_lds((const void*)gl_project_kernel<N, Q, false>, bytes);
+    if (e == hipSuccess) e = set_lds((const void*)gl_stage_kernel<N, Q, 0>, bytes);
+    if (e == hipSuccess) e = set_lds((const void*)gl_stage_kernel<N, Q, 1>, bytes);
     return e;
 }
 
 template <int N, int Q>
-static hipError_t dg_set_lds() {
-    hipError_t e = set_lds((const void*)gl_project_kernel<N, Q, true>, dg_project_lds(N - 1, Q));
-    if (e == hipSuccess) e = set_lds((const void*)dg_stage_kernel<N, Q>, dg_stage_lds(N - 1, Q));
+static hipError_t dg_set_lds(size_t bytes) {
+    hipError_t e = set_lds((const void*)gl_project_kernel<N, Q, true>, bytes);
+    if (e == hipSuccess) e = set_lds((const void*)dg_stage_kernel<N, Q>, bytes);
     return e;
 }
 
@@ -943,11 +1022,11 @@ hipError_t launch_gl_stage(bool dg, int p, int q, int variant, const StageArgs& 
     return hipErrorInvalidValue;
 }
 
-hipError_t gl_prepare(bool dg, int p, int q) {
+hipError_t gl_prepare(bool dg, int p, int q, size_t bytes) {
 #define NSFR_LDS(NN, QQ) \
-    if (p + 1 == NN && q == QQ) return gl_set_lds<NN, QQ>();
+    if (p + 1 == NN && q == QQ) return gl_set_lds<NN, QQ>(bytes);
 #define NSFR_DGL(NN, QQ) \
-    if (p + 1 == NN && q == QQ) return dg_set_lds<NN, QQ>();
+    if (p + 1 == NN && q == QQ) return dg_set_lds<NN, QQ>(bytes);
     if (dg) {
         NSFR_DG_TABLE(NSFR_DGL)
     } else {

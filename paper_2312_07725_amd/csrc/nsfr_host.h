@@ -135,8 +135,11 @@ hipError_t launch_gl_geometry(int p, int q, const GLOps* ops, int64_t E, const d
                               double* Cq, double* Cf, double* invWJ, double* Xq, hipStream_t s);
 // the projection (NSFR) or face-trace (DG) kernel, then the stage kernel
 // (one element per workgroup)
+// (one element per workgroup for NSFR, a.epb elements for DG)
 hipError_t launch_gl_stage(bool dg, int p, int q, int variant, const StageArgs& a, const GLArgs& g, hipStream_t s);
-size_t gl_lds_bytes(bool dg, int p, int q);   // dynamic LDS of the larger of the two kernels
-hipError_t gl_prepare(bool dg, int p, int q);  // allow that much dynamic LDS on the current device
+size_t gl_lds_bytes(bool dg, int p, int q, int epb);   // dynamic LDS of the larger of the two kernels
+int gl_max_epb(bool dg, int p, int q, size_t lds_max);  // largest elements per workgroup (0: none fits)
+int gl_default_epb(bool dg, int p, int q, int64_t E);
+hipError_t gl_prepare(bool dg, int p, int q, size_t bytes);  // allow that much dynamic LDS (current device)
 
 }  // namespace nsfr
