@@ -11,7 +11,7 @@
 //
 // Work decomposition: a workgroup owns `epb` elements. Every element has
 // 3 (p+1)^2 lines (p+1)^2 per direction; one thread owns one line. Its line's
-// primitive variables and metric column live in registers, all
+// metric column and residual live in registers (primitives in LDS), all
 // (p+1) p / 2 node pairs are evaluated once each (pair symmetry), and the two
 // endpoint face fluxes of the line are computed by the same thread, so every
 // face node's surface term belongs to exactly one thread (no atomics; the
@@ -50,16 +50,16 @@ __device__ __forceinline__ void line_pass(double* lr, int epb, int dir, const do
 
 // The whole stage for the `epb` elements starting at e0 (one workgroup).
 //
-// LDS per element: primitives [6][N3] and the metric columns of the three
-// directions in line-major order [dir][comp][position][line] (9 N3 doubles);
-// after the pair sweep the primitive block is reused for the residual
-// accumulator [5][N3]. Line data are read from LDS inside the pair loop, so a
-// thread keeps only the residual of its line in registers.
+// LDS per element: the primitives [6][N3] (padded); after the pair sweep the
+// block is reused for the residual accumulator [5][N3]. A line thread keeps
+// its line's metric column (3 N values, loaded from the line-major array) and
+// residual in registers and reads the primitives from LDS inside the pair
+// loop.
 template <int P, bool CWA, int VARIANT, int DISS>
 __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0, double* lds) {
     constexpr int N = P + 1, N2 = N * N, N3 = N2 * N, LINES = 3 * N2;
     constexpr int PN3 = padded_block<N>();          // padded stride of a primitive component
-    constexpr int LDSE = 6 * PN3 + 9 * N3;          // LDS doubles per element
+    constexpr int LDSE = 6 * PN3;                   // LDS doubles per element
     const int tid = threadIdx.x, nth = blockDim.x;
     const int epb = A.epb;
     const int64_t E = A.geo.E;
@@ -68,40 +68,49 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
     const double c1 = A.c1;
     const double pref = reference_pressure(A.Uin, SE, gm1);
 
-    // ---- 1. primitives and metric columns of the workgroup's elements -> LDS
+    // ---- line ownership (one thread per line)
+    const bool lt = tid < epb * LINES;
+    const int el = lt ? tid / LINES : 0;
+    const int rem = lt ? tid - el * LINES : 0;   // threads past the last line take line 0 (and stay idle)
+    const int dir = rem / N2;
+    const int l = rem - dir * N2;
+    const int64_t e = e0 + el;
+    const bool active = lt && (e < E);
+    // metric column of the line in registers, straight from the line-major
+    // array (coalesced across the lines of a direction; the loads overlap the
+    // staging below)
+    double cl[3][N];
+    if (active) {
+        const double* Cg = A.geo.Cline + ((int64_t)(3 * dir) * E + (active ? e : 0)) * N3 + l;
+#pragma unroll
+        for (int m = 0; m < 3; ++m)
+#pragma unroll
+            for (int a = 0; a < N; ++a) cl[m][a] = Cg[(int64_t)m * SE + a * N2];
+    }
+
+    // ---- 1. primitives of the workgroup's elements -> LDS
     for (int idx = tid; idx < epb * N3; idx += nth) {
-        int el = idx / N3, node = idx - el * N3;
-        int64_t e = e0 + el;
-        if (e < E) {
-            const double* U = A.Uin + e * N3 + node;
+        const int eli = idx / N3, node = idx - eli * N3;
+        const int64_t ee = e0 + eli;
+        if (ee < E) {
+            const double* U = A.Uin + ee * N3 + node;
             PrimR q = primitives_ref(U[0], U[SE], U[2 * SE], U[3 * SE], U[4 * SE], gm1, pref);
-            double* L = lds + el * LDSE + pad_node<N>(node);
+            double* L = lds + eli * LDSE + pad_node<N>(node);
             L[0] = q.rho;
             L[PN3] = q.u;
             L[2 * PN3] = q.v;
             L[3 * PN3] = q.w;
             L[4 * PN3] = q.pd;
             L[5 * PN3] = q.beta;
-            const double* Cg = A.geo.Cline + e * N3 + node;   // same offset in line-major order
-            double* Lc0 = lds + el * LDSE + 6 * PN3 + node;
-#pragma unroll
-            for (int k = 0; k < 9; ++k) Lc0[k * N3] = Cg[k * SE];
         }
     }
     __syncthreads();
 
-    // ---- 2. line ownership
-    const bool lt = tid < epb * LINES;
-    const int el = lt ? tid / LINES : 0;
-    const int rem = tid - el * LINES;
-    const int dir = rem / N2;
-    const int l = rem - dir * N2;
-    const int64_t e = e0 + el;
-    const bool active = lt && (e < E);
+    // ---- 2. line geometry
     int base, stride;
     line_geometry<N>(dir, l, base, stride);
     const double* Lp = lds + el * LDSE;                             // primitives
-    const double* Lc = lds + el * LDSE + 6 * PN3 + 3 * dir * N3 + l;   // metric column, [comp][pos][line]
+    auto cmet = [&](int m, int a) { return cl[m][a]; };
 
     // ---- 3. line residual: volume pairs, then the two endpoint face fluxes
     double R[5][N];
@@ -113,11 +122,11 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
 #pragma unroll
         for (int a = 0; a < N - 1; ++a) {
             const PrimR qa = lds_primr<PN3>(Lp, pad_node<N>(base + a * stride));
-            const double cax = Lc[a * N2], cay = Lc[N3 + a * N2], caz = Lc[2 * N3 + a * N2];
+            const double cax = cmet(0, a), cay = cmet(1, a), caz = cmet(2, a);
 #pragma unroll
             for (int b = a + 1; b < N; ++b) {
                 const PrimR qb = lds_primr<PN3>(Lp, pad_node<N>(base + b * stride));
-                const double cbx = Lc[b * N2], cby = Lc[N3 + b * N2], cbz = Lc[2 * N3 + b * N2];
+                const double cbx = cmet(0, b), cby = cmet(1, b), cbz = cmet(2, b);
                 double F[5];
                 // direction C(a) + C(b) = 2 N; the 1/2 is folded into S1h
                 ec_flux<VARIANT>(qa, qb, cax + cbx, cay + cby, caz + cbz, c1, pref, F);
@@ -144,8 +153,8 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
             const double cnx = Cn[0], cny = Cn[SE], cnz = Cn[2 * SE];
             const PrimR qn = primitives_ref(Un5[0], Un5[1], Un5[2], Un5[3], Un5[4], gm1, pref);
             const PrimR qo = lds_primr<PN3>(Lp, pad_node<N>(base + aown * stride));
-            const double nx = sg * (Lc[aown * N2] + cnx), ny = sg * (Lc[N3 + aown * N2] + cny),
-                         nz = sg * (Lc[2 * N3 + aown * N2] + cnz);
+            const double nx = sg * (cmet(0, aown) + cnx), ny = sg * (cmet(1, aown) + cny),
+                         nz = sg * (cmet(2, aown) + cnz);
             double F[5];
             ec_flux<VARIANT>(qo, qn, nx, ny, nz, c1, pref, F);
             if (DISS == 1) {
@@ -302,8 +311,14 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
 // threads per element of the stage kernel: one per line
 __host__ __device__ constexpr int stage_threads_per_elem(int n) { return 3 * n * n; }
 
+// Minimum waves per SIMD the register allocation must allow: at p = 3 a cap
+// of 168 VGPRs (3 waves; a few doubles spill) is faster than the 186-VGPR
+// allocation (2 waves); at p = 4, 5 the same cap spills heavily and is slower.
+__host__ __device__ constexpr int stage_min_waves(int p) { return p == 3 ? 3 : 1; }
+
 template <int P, bool CWA, int VARIANT, int DISS>
-__global__ __launch_bounds__(STAGE_BLOCK_MAX) void stage_kernel(StageArgs A) {
+__global__ __launch_bounds__(STAGE_BLOCK_MAX) __attribute__((amdgpu_waves_per_eu(stage_min_waves(P))))
+void stage_kernel(StageArgs A) {
     extern __shared__ double lds[];
     const int g = xcd_remap(blockIdx.x, gridDim.x);
     stage_body<P, CWA, VARIANT, DISS>(A, (int64_t)g * A.epb, lds);
@@ -343,7 +358,7 @@ hipError_t launch_ensemble_stage(const StageArgs* table, const int2* items, int 
 }
 
 // LDS per element of the stage kernel (doubles): primitives (padded) + metric columns
-static int stage_lds_doubles(int n) { return 6 * (n * n * n + n * n) + 9 * n * n * n; }
+static int stage_lds_doubles(int n) { return 6 * (n * n * n + n * n); }
 
 size_t stage_lds_bytes(int p, int epb) { return (size_t)epb * stage_lds_doubles(p + 1) * sizeof(double); }
 
