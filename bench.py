@@ -77,6 +77,11 @@ def load_counters(workload_key):
     return None
 
 
+def log(msg):
+    """Progress line on stderr (the JSON result line goes to stdout)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def timed(fn, reps, stream):
     """HIP-event time (s) of fn(reps) on `stream`, synchronised on both sides."""
     start = torch.cuda.Event(enable_timing=True)
@@ -221,6 +226,9 @@ def main():
     ap.add_argument("--ne", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="headline only: skip the extra measurements")
+    ap.add_argument("--extra", default="all",
+                    help="comma-separated extra blocks to run (rhs_16cubed, rhs_32cubed, adjoint, ensemble, gl, "
+                         "scheme_cost) or 'all'")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain elementwise copy of 2 x 1 GiB (reference for HBM counters)")
     args = ap.parse_args()
@@ -274,8 +282,14 @@ def main():
     d = g.diagnostics(U).cpu()
     extra = {"entropy_rate_rel": abs(float(d[0])) / float(d[1]), "unphysical_nodes": g.check_state(U),
              "nodes": nodes, "rhs_median_us": med * 1e6, "kernel_source_hash": kernel_source_hash()}
+    blocks = {"rhs_16cubed", "rhs_32cubed", "adjoint", "ensemble", "gl", "scheme_cost"}
+    want = blocks if args.extra == "all" else set(args.extra.split(","))
+    if want - blocks:
+        raise SystemExit(f"unknown extra blocks {sorted(want - blocks)}")
     if not args.quick:
         del g, U, out
+    if not args.quick and "rhs_16cubed" in want:
+        log("rhs_16cubed")
         extra["rhs_16cubed"] = {}
         for pp in (3, 4, 5):
             gg, UU, r = rhs_stats(nsfr, inputs, pp, 16, nsfr.c_hu(pp))
@@ -293,6 +307,8 @@ def main():
         gg, UU, r = rhs_stats(nsfr, inputs, 3, 16, 0.0)
         extra["rhs_16cubed"]["p3_c0"] = r
         del gg, UU
+    if not args.quick and "gl" in want:
+        log("gl")
         # uncollocated: Gauss-Legendre rule with q = p + 1 + overint points
         # (entropy projection kernel + hybridised stage kernel per rhs)
         extra["rhs_16cubed_gl"] = {}
@@ -300,9 +316,12 @@ def main():
             gg, UU, r = rhs_stats(nsfr, inputs, pp, 16, nsfr.c_hu(pp), reps=100, warm=10, quad="gl", overint=ov)
             del r["frac_hbm_roof"]
             r["q"] = pp + 1 + ov
-            r["vs_lgl_same_p"] = r["rhs_median_us"] / extra["rhs_16cubed"][f"p{pp}"]["rhs_median_us"]
+            if "rhs_16cubed" in extra:
+                r["vs_lgl_same_p"] = r["rhs_median_us"] / extra["rhs_16cubed"][f"p{pp}"]["rhs_median_us"]
             extra["rhs_16cubed_gl"][f"p{pp}_q{pp + 1 + ov}"] = r
             del gg, UU
+    if not args.quick and "scheme_cost" in want:
+        log("scheme_cost")
         # the paper's cost comparison (Sec. 7.4) on these kernels: NSFR-EC with
         # c_DG, conservative DG (Roe) and DG overintegrated to 2 (p + 1) points,
         # all on the Gauss-Legendre rule, warped TGV, one rhs
@@ -317,19 +336,26 @@ def main():
                     del gg, UU
                 extra["scheme_cost_gl"][f"ne{ne_}_p{pp}"] = {
                     "rhs_us": t, "nsfr_over_dg": t["nsfr"] / t["dg"], "dg_overint_over_nsfr": t["dg_overint"] / t["nsfr"]}
+    if not args.quick and "rhs_32cubed" in want:
+        log("rhs_32cubed")
         extra["rhs_32cubed"] = {}   # working sets of 0.3-1.1 GB: beyond the 256 MB last-level cache
         for pp in (3, 4, 5):
             gg, UU, r = rhs_stats(nsfr, inputs, pp, 32, nsfr.c_hu(pp), reps=200, warm=10)
             extra["rhs_32cubed"][f"p{pp}"] = r
             del gg, UU
         torch.cuda.empty_cache()
+    if not args.quick and "adjoint" in want:
+        log("adjoint")
         extra["adjoint_24cubed_p4"] = {"c0": adjoint_stats(nsfr, inputs, st, 0.0),
                                        "c_hu": adjoint_stats(nsfr, inputs, st, nsfr.c_hu(4), nsteps=0)}
         torch.cuda.empty_cache()
+    if not args.quick and "ensemble" in want:
+        log("ensemble")
         extra["ensemble"] = ensemble_stats(nsfr, inputs, st)
 
     cpu = None
     if not args.no_cpu:
+        log("cpu_baseline")
         cpu = cpu_baseline(p, ne, c)
 
     line = {

@@ -50,16 +50,24 @@ __device__ __forceinline__ void line_pass(double* lr, int epb, int dir, const do
 
 // The whole stage for the `epb` elements starting at e0 (one workgroup).
 //
-// LDS per element: the primitives [6][N3] (padded); after the pair sweep the
-// block is reused for the residual accumulator [5][N3]. A line thread keeps
-// its line's metric column (3 N values, loaded from the line-major array) and
-// residual in registers and reads the primitives from LDS inside the pair
-// loop.
+// Where a line thread reads its line's metric column (3 N values): at p = 3
+// from LDS (all nine columns staged line-major, [dir][comp][position][line],
+// 9 N3 doubles per element), elsewhere from registers loaded straight from
+// the line-major array. Under the 3-waves-per-SIMD register cap of p = 3 the
+// LDS copy can be re-read instead of spilled; at p = 4, 5 (no cap) holding
+// the column in registers is slightly faster and saves the LDS.
+__host__ __device__ constexpr bool metric_in_lds(int p) { return p == 3; }
+
+// LDS per element: the primitives [6][N3] (padded), and at p = 3 the metric
+// columns; after the pair sweep the primitive block is reused for the
+// residual accumulator [5][N3]. A line thread keeps its residual in registers
+// and reads the primitives from LDS inside the pair loop.
 template <int P, bool CWA, int VARIANT, int DISS>
 __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0, double* lds) {
     constexpr int N = P + 1, N2 = N * N, N3 = N2 * N, LINES = 3 * N2;
     constexpr int PN3 = padded_block<N>();          // padded stride of a primitive component
-    constexpr int LDSE = 6 * PN3;                   // LDS doubles per element
+    constexpr bool MLDS = metric_in_lds(P);
+    constexpr int LDSE = 6 * PN3 + (MLDS ? 9 * N3 : 0);   // LDS doubles per element
     const int tid = threadIdx.x, nth = blockDim.x;
     const int epb = A.epb;
     const int64_t E = A.geo.E;
@@ -80,7 +88,7 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
     // array (coalesced across the lines of a direction; the loads overlap the
     // staging below)
     double cl[3][N];
-    if (active) {
+    if (!MLDS && active) {
         const double* Cg = A.geo.Cline + ((int64_t)(3 * dir) * E + (active ? e : 0)) * N3 + l;
 #pragma unroll
         for (int m = 0; m < 3; ++m)
@@ -88,7 +96,7 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
             for (int a = 0; a < N; ++a) cl[m][a] = Cg[(int64_t)m * SE + a * N2];
     }
 
-    // ---- 1. primitives of the workgroup's elements -> LDS
+    // ---- 1. primitives (and at p = 3 the metric columns) of the workgroup's elements -> LDS
     for (int idx = tid; idx < epb * N3; idx += nth) {
         const int eli = idx / N3, node = idx - eli * N3;
         const int64_t ee = e0 + eli;
@@ -102,6 +110,12 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
             L[3 * PN3] = q.w;
             L[4 * PN3] = q.pd;
             L[5 * PN3] = q.beta;
+            if (MLDS) {
+                const double* Cg = A.geo.Cline + ee * N3 + node;   // same offset in line-major order
+                double* Lc0 = lds + eli * LDSE + 6 * PN3 + node;
+#pragma unroll
+                for (int k = 0; k < 9; ++k) Lc0[k * N3] = Cg[k * SE];
+            }
         }
     }
     __syncthreads();
@@ -110,7 +124,8 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
     int base, stride;
     line_geometry<N>(dir, l, base, stride);
     const double* Lp = lds + el * LDSE;                             // primitives
-    auto cmet = [&](int m, int a) { return cl[m][a]; };
+    const double* Lc = lds + el * LDSE + 6 * PN3 + 3 * dir * N3 + l;   // [comp][position][line] (p = 3)
+    auto cmet = [&](int m, int a) { return MLDS ? Lc[m * N3 + a * N2] : cl[m][a]; };
 
     // ---- 3. line residual: volume pairs, then the two endpoint face fluxes
     double R[5][N];
@@ -358,7 +373,7 @@ hipError_t launch_ensemble_stage(const StageArgs* table, const int2* items, int 
 }
 
 // LDS per element of the stage kernel (doubles): primitives (padded) + metric columns
-static int stage_lds_doubles(int n) { return 6 * (n * n * n + n * n); }
+static int stage_lds_doubles(int n) { return 6 * (n * n * n + n * n) + (metric_in_lds(n - 1) ? 9 * n * n * n : 0); }
 
 size_t stage_lds_bytes(int p, int epb) { return (size_t)epb * stage_lds_doubles(p + 1) * sizeof(double); }
 
