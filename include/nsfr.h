@@ -205,7 +205,9 @@ nsfr_status nsfr_kinetic_energy(nsfr_ctx* ctx, const double* U, double* ke_dev, 
  * p <= 0 or a NaN; returns NSFR_EUNPHYSICAL if that number is positive. */
 nsfr_status nsfr_check_state(nsfr_ctx* ctx, const double* U, int32_t* bad_host);
 
-/* ---- ensembles of independent flows, one launch per RK stage ------------ */
+/* ---- ensembles of independent flows: per RK stage one launch per kind of
+ * flow present (degree, c != 0, flux variant), each specialised like the
+ * single-flow stage kernel --------------------------------------------- */
 typedef struct nsfr_ens nsfr_ens;
 
 /* n_flows configurations (any mix of p, ne, c and flux; surface_diss,
@@ -218,15 +220,16 @@ nsfr_status nsfr_ens_destroy(nsfr_ens* ens);
  * ensemble's later calls enqueue their work. */
 nsfr_status nsfr_ens_set_stream(nsfr_ens* ens, void* hip_stream);
 nsfr_status nsfr_ens_offsets(const nsfr_ens* ens, int64_t* offsets_host);
-/* Residual / rhs of every flow at time t in one launch. */
+/* Right-hand side of every flow at time t (one launch per kind). */
 nsfr_status nsfr_ens_rhs(nsfr_ens* ens, const double* U, double* dUdt, double t);
 /* One RK4 step of every flow, in place; dt_dev holds one step size per flow;
- * work holds 3 packed-state-sized arrays. Four launches, one per stage. */
+ * work holds 3 packed-state-sized arrays. Four stages, each one launch per
+ * kind. */
 nsfr_status nsfr_ens_rk4_step(nsfr_ens* ens, double* U, const double* dt_dev, double t, double* work);
 /* nsteps steps replayed from a HIP graph of one ensemble step. */
 nsfr_status nsfr_ens_rk4_run(nsfr_ens* ens, double* U, const double* dt_dev, double t,
                              int32_t nsteps, double* work);
-/* Elements per work item for degree p (2..5) used by the ensemble kernel
+/* Elements per work item for degree p (2..5) used by the ensemble kernels
  * (the same bounds as the config's tile); epb = 0 restores the default. */
 nsfr_status nsfr_ens_set_tile(nsfr_ens* ens, int32_t p, int32_t epb);
 

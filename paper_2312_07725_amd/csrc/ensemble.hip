@@ -1,12 +1,14 @@
-// Ensembles of independent flows: one persistent launch per RK stage covers
-// every flow, whatever its degree and mesh size.
+// Ensembles of independent flows: each RK stage of every flow, whatever its
+// degree and mesh size, in one launch per kind of flow present (degree,
+// c != 0, flux variant).
 //
 // Each flow owns an ordinary context (operators, warped mesh, metrics). The
 // packed state is the concatenation of the flows' state arrays. A device table
 // holds one StageArgs per (stage, flow) and a work list holds (flow, first
-// element) items, sorted by decreasing cost per item; the persistent kernel
-// walks the list with a static stride. Tiles (elements per item) are per
-// degree and can be set from an autotuned table.
+// element) items, grouped by kind and within a kind sorted by decreasing
+// cost; a kind's launch runs one workgroup per item of its slice with the
+// kernel specialised for that kind. Tiles (elements per item) are per degree
+// and can be set from an autotuned table.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -23,7 +25,8 @@ constexpr int NMODES = 5;   // RK1..RK4, RHS
 
 int mode_slot(int mode) { return mode == MODE_RHS ? 4 : mode - MODE_RK1; }
 
-int default_ens_epb(int p) { return max_ensemble_epb(p); }
+int default_ens_epb(int p) { return default_epb(p); }
+constexpr int NKINDS = 16;
 }  // namespace
 
 struct nsfr_ens {
@@ -36,11 +39,9 @@ struct nsfr_ens {
     std::vector<int> kinds;
     int epb[4] = {0, 0, 0, 0};     // per p = 2..5
     StageArgs* dtab = nullptr;     // [NMODES][nf]
-    int* dkinds = nullptr;
-    int2* ditems = nullptr;
+    int2* ditems = nullptr;        // work list, grouped by kind
     int nitems = 0;
-    size_t lds = 0;
-    int grid = 0;
+    int kbeg[NKINDS] = {}, kcnt[NKINDS] = {};   // each kind's slice of the work list
     bool items_ok = false;
     const void* key[NMODES][4] = {};
     hipGraph_t graph = nullptr;
@@ -62,7 +63,6 @@ static void ens_free(nsfr_ens* s) {
     if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
     if (s->graph) (void)hipGraphDestroy(s->graph);
     if (s->dtab) (void)hipFree(s->dtab);
-    if (s->dkinds) (void)hipFree(s->dkinds);
     if (s->ditems) (void)hipFree(s->ditems);
     for (auto* c : s->flows)
         if (c) nsfr_destroy(c);
@@ -71,9 +71,8 @@ static void ens_free(nsfr_ens* s) {
 
 // (re)build the sorted work list for the current tiles
 static nsfr_status build_items(nsfr_ens* s) {
-    struct Item { int f; int e0; double cost; };
+    struct Item { int f; int e0; int kind; double cost; };
     std::vector<Item> items;
-    size_t lds = 0;
     for (int f = 0; f < s->nf; ++f) {
         const nsfr_config& c = s->cfgs[f];
         const int n = c.p + 1, n3 = n * n * n;
@@ -82,11 +81,19 @@ static nsfr_status build_items(nsfr_ens* s) {
         const double per_node_pairs = 1.5 * (n - 1) + 6.0 / n;
         for (int64_t e0 = 0; e0 < E; e0 += epb) {
             int cnt = (int)std::min<int64_t>(epb, E - e0);
-            items.push_back({f, (int)e0, cnt * n3 * per_node_pairs});
+            items.push_back({f, (int)e0, s->kinds[f], cnt * n3 * per_node_pairs});
         }
-        lds = std::max(lds, stage_lds_bytes(c.p, epb));
     }
-    std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) { return a.cost > b.cost; });
+    std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) {
+        return a.kind != b.kind ? a.kind < b.kind : a.cost > b.cost;
+    });
+    std::fill(s->kbeg, s->kbeg + NKINDS, 0);
+    std::fill(s->kcnt, s->kcnt + NKINDS, 0);
+    for (size_t i = 0; i < items.size(); ++i) {
+        const int k = items[i].kind;
+        if (s->kcnt[k] == 0) s->kbeg[k] = (int)i;
+        ++s->kcnt[k];
+    }
     std::vector<int2> h(items.size());
     for (size_t i = 0; i < items.size(); ++i) h[i] = make_int2(items[i].f, items[i].e0);
     if (s->ditems) (void)hipFree(s->ditems);
@@ -94,10 +101,6 @@ static nsfr_status build_items(nsfr_ens* s) {
     HIP_TRY(hipMalloc((void**)&s->ditems, std::max<size_t>(1, h.size()) * sizeof(int2)));
     HIP_TRY(hipMemcpy(s->ditems, h.data(), h.size() * sizeof(int2), hipMemcpyHostToDevice));
     s->nitems = (int)h.size();
-    s->lds = lds;
-    int cus = 0;
-    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s->dev));
-    s->grid = std::max(1, std::min(s->nitems, 2 * cus));
     s->items_ok = true;
     std::memset(s->key, 0, sizeof(s->key));   // tables carry epb: rebuild them
     return NSFR_OK;
@@ -131,11 +134,15 @@ static nsfr_status build_table(nsfr_ens* s, int mode, const double* Uin, const d
 }
 
 static nsfr_status launch(nsfr_ens* s, int mode, hipStream_t st) {
-    hipError_t e = launch_ensemble_stage(s->dtab + (size_t)mode_slot(mode) * s->nf, s->ditems, s->nitems,
-                                         s->dkinds, s->lds, s->grid, st);
-    if (e != hipSuccess) {
-        set_error(std::string("ensemble kernel launch: ") + hipGetErrorString(e));
-        return NSFR_EHIP;
+    const StageArgs* tab = s->dtab + (size_t)mode_slot(mode) * s->nf;
+    for (int k = 0; k < NKINDS; ++k) {
+        if (s->kcnt[k] == 0) continue;
+        const int p = k / 4 + 2;
+        hipError_t e = launch_ensemble_kind(k, tab, s->ditems + s->kbeg[k], s->kcnt[k], s->epb[p - 2], st);
+        if (e != hipSuccess) {
+            set_error(std::string("ensemble kernel launch: ") + hipGetErrorString(e));
+            return NSFR_EHIP;
+        }
     }
     return NSFR_OK;
 }
@@ -199,16 +206,10 @@ nsfr_status nsfr_ens_create(const nsfr_config* cfgs, int32_t n, void* stream, ns
         s->kinds.push_back(ctx_kind(ctx));
         s->offs.push_back(s->offs.back() + ctx_state_size(ctx));
     }
-    if (hipMalloc((void**)&s->dtab, (size_t)NMODES * n * sizeof(StageArgs)) != hipSuccess ||
-        hipMalloc((void**)&s->dkinds, (size_t)n * sizeof(int)) != hipSuccess) {
+    if (hipMalloc((void**)&s->dtab, (size_t)NMODES * n * sizeof(StageArgs)) != hipSuccess) {
         set_error("hipMalloc failed for the ensemble tables");
         ens_free(s);
         return NSFR_ENOMEM;
-    }
-    if (hipMemcpy(s->dkinds, s->kinds.data(), n * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
-        set_error("copy of the ensemble kind table failed");
-        ens_free(s);
-        return NSFR_EHIP;
     }
     nsfr_status st = build_items(s);
     if (st != NSFR_OK) {
@@ -252,8 +253,8 @@ nsfr_status nsfr_ens_set_tile(nsfr_ens* s, int32_t p, int32_t epb) {
         return NSFR_EINVAL;
     }
     if (epb == 0) epb = default_ens_epb(p);
-    if (epb < 1 || epb > max_ensemble_epb(p)) {
-        set_error("tile does not fit the ensemble workgroup (512 threads) or the LDS budget");
+    if (epb < 1 || epb > max_epb(p)) {
+        set_error("tile does not fit the stage workgroup (512 threads) or the LDS budget");
         return NSFR_EINVAL;
     }
     s->epb[p - 2] = epb;

@@ -100,7 +100,6 @@ hipError_t launch_geometry(int p, const Ops& ops, int nx, int ny, int nz, double
 hipError_t launch_stage(int p, bool cwa, int variant, const StageArgs& a, hipStream_t s);
 int default_epb(int p);
 size_t stage_lds_bytes(int p, int epb);
-int max_ensemble_epb(int p);
 int max_epb(int p);
 hipError_t launch_geometry_export(int p, int64_t E, const double* Cline, double* C, hipStream_t s);
 hipError_t launch_max_wavespeed(int64_t nnodes, const double* U, double gamma, double* partial, int nblk,
@@ -126,8 +125,9 @@ constexpr int kind_code(int p, bool cwa, int variant) { return (p - 2) * 4 + (cw
 StageArgs ctx_stage_args(const nsfr_ctx* c);
 int ctx_kind(const nsfr_ctx* c);
 int64_t ctx_state_size(const nsfr_ctx* c);
-hipError_t launch_ensemble_stage(const StageArgs* table, const int2* items, int nitems, const int* kinds,
-                                 size_t lds_bytes, int grid, hipStream_t s);
+// one stage of every ensemble flow of one kind: one workgroup per work item
+hipError_t launch_ensemble_kind(int kind, const StageArgs* table, const int2* items, int nitems, int epb,
+                                hipStream_t s);
 
 // Gauss-Legendre variant (gl.hip): p = 2..5 with q = p + 1 .. p + 4 points
 // (NSFR) or q = p + 1 .. 2 (p + 1) points (conservative DG, dg = true)

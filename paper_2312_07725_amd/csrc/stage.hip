@@ -339,36 +339,26 @@ void stage_kernel(StageArgs A) {
     stage_body<P, CWA, VARIANT, DISS>(A, (int64_t)g * A.epb, lds);
 }
 
-// Persistent ensemble kernel: every workgroup walks the work list (flow,
-// first element) with a static stride, so the assignment is deterministic;
-// the list is sorted by decreasing cost. The variant of the body is chosen
-// per item from the flow's kind code (uniform across the workgroup).
-__global__ __launch_bounds__(STAGE_BLOCK_MAX) void ensemble_kernel(const StageArgs* __restrict__ table,
-                                                                   const int2* __restrict__ items, int nitems,
-                                                                   const int* __restrict__ kinds) {
+// Ensemble launch for one kind of flow (degree, c != 0, flux variant): one
+// workgroup per work item (flow, first element) of the kind's slice of the
+// work list, the flow's StageArgs read from the device table. The kernel is
+// specialised like the single-flow one (block size, LDS and register budget
+// of its own degree), so an ensemble step is one launch per kind present.
+template <int P, bool CWA, int VARIANT>
+__global__ __launch_bounds__(STAGE_BLOCK_MAX) __attribute__((amdgpu_waves_per_eu(stage_min_waves(P))))
+void ensemble_kind_kernel(const StageArgs* __restrict__ table, const int2* __restrict__ items) {
     extern __shared__ double lds[];
-    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
-        __syncthreads();   // the previous item's LDS reads are complete
-        const int2 w = items[it];
-        const int f = __builtin_amdgcn_readfirstlane(w.x);
-        const int64_t e0 = __builtin_amdgcn_readfirstlane(w.y);
-        const StageArgs& A = table[f];
-        switch (__builtin_amdgcn_readfirstlane(kinds[f])) {
-#define NSFR_CASE(P, C, V) \
-    case kind_code(P, C, V): stage_body<P, C, V, 0>(A, e0, lds); break;
-            NSFR_CASE(2, false, 0) NSFR_CASE(2, false, 1) NSFR_CASE(2, true, 0) NSFR_CASE(2, true, 1)
-            NSFR_CASE(3, false, 0) NSFR_CASE(3, false, 1) NSFR_CASE(3, true, 0) NSFR_CASE(3, true, 1)
-            NSFR_CASE(4, false, 0) NSFR_CASE(4, false, 1) NSFR_CASE(4, true, 0) NSFR_CASE(4, true, 1)
-            NSFR_CASE(5, false, 0) NSFR_CASE(5, false, 1) NSFR_CASE(5, true, 0) NSFR_CASE(5, true, 1)
-#undef NSFR_CASE
-            default: break;
-        }
-    }
+    const int2 w = items[blockIdx.x];
+    const int f = __builtin_amdgcn_readfirstlane(w.x);
+    const int64_t e0 = __builtin_amdgcn_readfirstlane(w.y);
+    stage_body<P, CWA, VARIANT, 0>(table[f], e0, lds);
 }
 
-hipError_t launch_ensemble_stage(const StageArgs* table, const int2* items, int nitems, const int* kinds,
-                                 size_t lds_bytes, int grid, hipStream_t s) {
-    ensemble_kernel<<<grid, STAGE_BLOCK_MAX, lds_bytes, s>>>(table, items, nitems, kinds);
+template <int P, bool CWA, int V>
+static hipError_t launch_kind_t(const StageArgs* table, const int2* items, int nitems, int epb, hipStream_t s) {
+    constexpr int N = P + 1;
+    const int threads = ((epb * stage_threads_per_elem(N) + 63) / 64) * 64;
+    ensemble_kind_kernel<P, CWA, V><<<nitems, threads, stage_lds_bytes(P, epb), s>>>(table, items);
     return hipGetLastError();
 }
 
@@ -384,8 +374,6 @@ int max_epb(int p) {
     return by_threads < by_lds ? by_threads : by_lds;
 }
 
-// the ensemble kernel runs workgroups of STAGE_BLOCK_MAX threads too
-int max_ensemble_epb(int p) { return max_epb(p); }
 
 int default_epb(int p) {
     switch (p) {
@@ -422,6 +410,22 @@ template <int P>
 static hipError_t launch_p(bool cwa, int v, const StageArgs& a, hipStream_t s) {
     if (cwa) return v ? launch_d<P, true, 1>(a, s) : launch_d<P, true, 0>(a, s);
     return v ? launch_d<P, false, 1>(a, s) : launch_d<P, false, 0>(a, s);
+}
+
+hipError_t launch_ensemble_kind(int kind, const StageArgs* table, const int2* items, int nitems, int epb,
+                                hipStream_t s) {
+    const int p = kind / 4 + 2;
+    if (nitems < 1 || epb < 1 || epb > max_epb(p)) return hipErrorInvalidValue;
+    switch (kind) {
+#define NSFR_KIND(P, C, V) \
+    case kind_code(P, C, V): return launch_kind_t<P, C, V>(table, items, nitems, epb, s);
+        NSFR_KIND(2, false, 0) NSFR_KIND(2, false, 1) NSFR_KIND(2, true, 0) NSFR_KIND(2, true, 1)
+        NSFR_KIND(3, false, 0) NSFR_KIND(3, false, 1) NSFR_KIND(3, true, 0) NSFR_KIND(3, true, 1)
+        NSFR_KIND(4, false, 0) NSFR_KIND(4, false, 1) NSFR_KIND(4, true, 0) NSFR_KIND(4, true, 1)
+        NSFR_KIND(5, false, 0) NSFR_KIND(5, false, 1) NSFR_KIND(5, true, 0) NSFR_KIND(5, true, 1)
+#undef NSFR_KIND
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_stage(int p, bool cwa, int variant, const StageArgs& a, hipStream_t s) {
