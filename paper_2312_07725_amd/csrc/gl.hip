@@ -305,9 +305,16 @@ __global__ __launch_bounds__(GL_BLOCK) void gl_project_kernel(const GLOps* __res
     }
 }
 
+// Minimum waves per SIMD the register allocation of the NSFR stage must
+// allow: at q = 5 a cap of 256 registers (2 waves, 128 B of spill) is faster
+// than the uncapped allocation (1 wave); from q = 6 the cap spills 0.25-1.7 KB
+// per lane and is slower, and up to q = 4 the kernel fits 2 waves without it.
+__host__ __device__ constexpr int gl_stage_min_waves(int q) { return q == 5 ? 2 : 1; }
+
 // ---- the stage: one element per workgroup
 template <int N, int Q, int VARIANT>
-__global__ __launch_bounds__(GL_BLOCK) void gl_stage_kernel(StageArgs A, GLArgs G) {
+__global__ __launch_bounds__(GL_BLOCK) __attribute__((amdgpu_waves_per_eu(gl_stage_min_waves(Q))))
+void gl_stage_kernel(StageArgs A, GLArgs G) {
     constexpr int N2 = N * N, N3 = N2 * N, Q2 = Q * Q, Q3 = Q2 * Q;
     extern __shared__ double lds[];
     double* mchi = lds;               // Q x N
@@ -378,8 +385,12 @@ __global__ __launch_bounds__(GL_BLOCK) void gl_stage_kernel(StageArgs A, GLArgs 
     }
     __syncthreads();
 
-    // 2. one thread per line: pairs along the line, pairs with the two end face
-    //    points (weights t_L, t_R), and the surface flux at both ends
+    // 2. one thread per line, in two passes whose register footprints do not
+    //    add up: (a) the volume pairs along the line, accumulated into BB in a
+    //    fixed direction order; (b) the pairs of every volume point with the two
+    //    end face points (weights t_L, t_R) and the surface numerical flux at
+    //    both ends, added into BB in the same order, face residuals into RF
+    //    (each face point belongs to one line)
     const int lt = tid;
     const bool active = lt < 3 * Q2;
     const int dir = active ? lt / Q2 : 0;
@@ -387,120 +398,123 @@ __global__ __launch_bounds__(GL_BLOCK) void gl_stage_kernel(StageArgs A, GLArgs 
     const int t1 = l % Q, t2 = l / Q;
     const int base = dir == 0 ? Q * t1 + Q2 * t2 : (dir == 1 ? t1 + Q2 * t2 : t1 + Q * t2);
     const int stride = dir == 0 ? 1 : (dir == 1 ? Q : Q2);
-    double Rv[5][Q], Rf[2][5];
-#pragma unroll
-    for (int s = 0; s < 5; ++s) {
-#pragma unroll
-        for (int a = 0; a < Q; ++a) Rv[s][a] = 0.0;
-        Rf[0][s] = Rf[1][s] = 0.0;
-    }
-    if (active) {
-        const double* Cl = G.geo.Cq + (int64_t)(3 * dir) * E * Q3 + e * Q3 + l;   // [comp][pos Q^2]
-        const int64_t CS = E * Q3;
-        auto volp = [&](int a) {
-            const int t = base + a * stride;
-            return PrimR{BA[t], BA[Q3 + t], BA[2 * Q3 + t], BA[3 * Q3 + t], BA[4 * Q3 + t], BA[5 * Q3 + t]};
-        };
-        // volume-volume pairs (S/2 folded into msq, direction C(a) + C(b))
-#pragma unroll
-        for (int a = 0; a < Q - 1; ++a) {
-            const PrimR qa = volp(a);
-            const double cax = Cl[a * Q2], cay = Cl[CS + a * Q2], caz = Cl[2 * CS + a * Q2];
-#pragma unroll
-            for (int b = a + 1; b < Q; ++b) {
-                const PrimR qb = volp(b);
-                double F[5];
-                ec_flux<VARIANT>(qa, qb, cax + Cl[b * Q2], cay + Cl[CS + b * Q2], caz + Cl[2 * CS + b * Q2], c1, pref,
-                                 F);
-                const double sab = msq[a * Q + b];
-#pragma unroll
-                for (int s = 0; s < 5; ++s) {
-                    Rv[s][a] = __builtin_fma(sab, F[s], Rv[s][a]);
-                    Rv[s][b] = __builtin_fma(-sab, F[s], Rv[s][b]);
-                }
-            }
-        }
-        // the two ends of the line
-#pragma unroll
-        for (int side = 0; side < 2; ++side) {
-            const int f = 2 * dir + side;
-            const double sg = side ? 1.0 : -1.0;
-            const double* tw = side ? mtr : mtl;
-            const double* Fp = FP + f * 6 * Q2 + l;
-            const PrimR qf = PrimR{Fp[0], Fp[Q2], Fp[2 * Q2], Fp[3 * Q2], Fp[4 * Q2], Fp[5 * Q2]};
-            const double* Cfo = G.geo.Cf + ((int64_t)(f * 3) * E + e) * Q2 + l;
-            const int64_t FS = E * Q2;
-            const double cfx = Cfo[0], cfy = Cfo[FS], cfz = Cfo[2 * FS];
-            // volume-face pairs: +/- t[a] W_perp F(u~_a, u~_f; (C_a + C_f)/2) on the volume
-            // point, the opposite on the face point
-#pragma unroll
-            for (int a = 0; a < Q; ++a) {
-                const PrimR qa = volp(a);
-                double F[5];
-                ec_flux<VARIANT>(qa, qf, Cl[a * Q2] + cfx, Cl[CS + a * Q2] + cfy, Cl[2 * CS + a * Q2] + cfz, c1,
-                                 pref, F);
-                const double wgt = 0.5 * sg * tw[a];
-#pragma unroll
-                for (int s = 0; s < 5; ++s) {
-                    Rv[s][a] = __builtin_fma(wgt, F[s], Rv[s][a]);
-                    Rf[side][s] = __builtin_fma(-wgt, F[s], Rf[side][s]);
-                }
-            }
-            // surface numerical flux with the neighbour's face point
-            const int en = A.geo.nbr[(int64_t)f * E + e];
-            const int fn = 2 * dir + (1 - side);
-            double vn[5];
-#pragma unroll
-            for (int s = 0; s < 5; ++s) vn[s] = G.ft[((int64_t)(fn * 5 + s) * E + en) * Q2 + l];
-            const PrimR qn = prims_from_entropy(vn, gm1, gamma, pref);
-            const double* Cfn = G.geo.Cf + ((int64_t)(fn * 3) * E + en) * Q2 + l;
-            const double nx = 0.5 * sg * (cfx + Cfn[0]), ny = 0.5 * sg * (cfy + Cfn[FS]),
-                         nz = 0.5 * sg * (cfz + Cfn[2 * FS]);
-            double F[5];
-            ec_flux<VARIANT>(qf, qn, nx, ny, nz, c1, pref, F);
-            if (A.diss == 1) {
-                const double gmr = gm1;
-                auto cons = [&](const PrimR& q, double out[5]) {
-                    out[0] = q.rho;
-                    out[1] = q.rho * q.u;
-                    out[2] = q.rho * q.v;
-                    out[3] = q.rho * q.w;
-                    out[4] = (pref + q.pd) / gmr + 0.5 * q.rho * (q.u * q.u + q.v * q.v + q.w * q.w);
-                };
-                double Uo[5], Un[5];
-                cons(qf, Uo);
-                cons(qn, Un);
-                llf_add(qf, qn, Uo, Un, nx, ny, nz, gamma, pref, F);
-            } else if (A.diss == 2) {
-                roe_add(qf, qn, nx, ny, nz, gamma, pref, F);
-            }
-#pragma unroll
-            for (int s = 0; s < 5; ++s) Rf[side][s] += F[s];
-        }
-    }
-    __syncthreads();   // the volume primitives (BA) are no longer read
-    // volume residuals of the three directions into BB (fixed order), face
-    // residuals into RF (each face point belongs to one line)
     const double wperp = mw[t1] * mw[t2];
-    for (int ph = 0; ph < 3; ++ph) {
-        if (active && dir == ph) {
+    const double* Cl = G.geo.Cq + (int64_t)(3 * dir) * E * Q3 + e * Q3 + l;   // [comp][pos Q^2]
+    const int64_t CS = E * Q3;
+    const int64_t FS = E * Q2;
+    auto volp = [&](int a) {
+        const int t = base + a * stride;
+        return PrimR{BA[t], BA[Q3 + t], BA[2 * Q3 + t], BA[3 * Q3 + t], BA[4 * Q3 + t], BA[5 * Q3 + t]};
+    };
+    // the line's volume residual into BB: phase ph stores (first pass) or adds
+    auto accumulate = [&](double (&Rv)[5][Q], bool first) {
+        for (int ph = 0; ph < 3; ++ph) {
+            if (active && dir == ph) {
 #pragma unroll
-            for (int s = 0; s < 5; ++s)
+                for (int s = 0; s < 5; ++s)
+#pragma unroll
+                    for (int a = 0; a < Q; ++a) {
+                        const double v = Rv[s][a] * wperp;
+                        double* x = BB + s * Q3 + base + a * stride;
+                        if (first && ph == 0) *x = v;
+                        else *x += v;
+                    }
+            }
+            __syncthreads();
+        }
+    };
+    {   // (a) volume-volume pairs (S/2 folded into msq, direction C(a) + C(b))
+        double Rv[5][Q];
+#pragma unroll
+        for (int s = 0; s < 5; ++s)
+#pragma unroll
+            for (int a = 0; a < Q; ++a) Rv[s][a] = 0.0;
+        if (active) {
+#pragma unroll
+            for (int a = 0; a < Q - 1; ++a) {
+                const PrimR qa = volp(a);
+                const double cax = Cl[a * Q2], cay = Cl[CS + a * Q2], caz = Cl[2 * CS + a * Q2];
+#pragma unroll
+                for (int b = a + 1; b < Q; ++b) {
+                    const PrimR qb = volp(b);
+                    double F[5];
+                    ec_flux<VARIANT>(qa, qb, cax + Cl[b * Q2], cay + Cl[CS + b * Q2], caz + Cl[2 * CS + b * Q2], c1,
+                                     pref, F);
+                    const double sab = msq[a * Q + b];
+#pragma unroll
+                    for (int s = 0; s < 5; ++s) {
+                        Rv[s][a] = __builtin_fma(sab, F[s], Rv[s][a]);
+                        Rv[s][b] = __builtin_fma(-sab, F[s], Rv[s][b]);
+                    }
+                }
+            }
+        }
+        accumulate(Rv, true);
+    }
+    {   // (b) the two ends of the line
+        double Rv[5][Q];
+#pragma unroll
+        for (int s = 0; s < 5; ++s)
+#pragma unroll
+            for (int a = 0; a < Q; ++a) Rv[s][a] = 0.0;
+        if (active) {
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                const int f = 2 * dir + side;
+                const double sg = side ? 1.0 : -1.0;
+                const double* tw = side ? mtr : mtl;
+                const double* Fp = FP + f * 6 * Q2 + l;
+                const PrimR qf = PrimR{Fp[0], Fp[Q2], Fp[2 * Q2], Fp[3 * Q2], Fp[4 * Q2], Fp[5 * Q2]};
+                const double* Cfo = G.geo.Cf + ((int64_t)(f * 3) * E + e) * Q2 + l;
+                const double cfx = Cfo[0], cfy = Cfo[FS], cfz = Cfo[2 * FS];
+                double rf[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+                // volume-face pairs: +/- t[a] W_perp F(u~_a, u~_f; (C_a + C_f)/2) on the
+                // volume point, the opposite on the face point
 #pragma unroll
                 for (int a = 0; a < Q; ++a) {
-                    const double v = Rv[s][a] * wperp;
-                    double* x = BB + s * Q3 + base + a * stride;
-                    if (ph == 0) *x = v;
-                    else *x += v;
+                    const PrimR qa = volp(a);
+                    double F[5];
+                    ec_flux<VARIANT>(qa, qf, Cl[a * Q2] + cfx, Cl[CS + a * Q2] + cfy, Cl[2 * CS + a * Q2] + cfz, c1,
+                                     pref, F);
+                    const double wgt = 0.5 * sg * tw[a];
+#pragma unroll
+                    for (int s = 0; s < 5; ++s) {
+                        Rv[s][a] = __builtin_fma(wgt, F[s], Rv[s][a]);
+                        rf[s] = __builtin_fma(-wgt, F[s], rf[s]);
+                    }
                 }
+                // surface numerical flux with the neighbour's face point
+                const int en = A.geo.nbr[(int64_t)f * E + e];
+                const int fn = 2 * dir + (1 - side);
+                double vn[5];
+#pragma unroll
+                for (int s = 0; s < 5; ++s) vn[s] = G.ft[((int64_t)(fn * 5 + s) * E + en) * Q2 + l];
+                const PrimR qn = prims_from_entropy(vn, gm1, gamma, pref);
+                const double* Cfn = G.geo.Cf + ((int64_t)(fn * 3) * E + en) * Q2 + l;
+                const double nx = 0.5 * sg * (cfx + Cfn[0]), ny = 0.5 * sg * (cfy + Cfn[FS]),
+                             nz = 0.5 * sg * (cfz + Cfn[2 * FS]);
+                double F[5];
+                ec_flux<VARIANT>(qf, qn, nx, ny, nz, c1, pref, F);
+                if (A.diss == 1) {
+                    auto cons = [&](const PrimR& q, double out[5]) {
+                        out[0] = q.rho;
+                        out[1] = q.rho * q.u;
+                        out[2] = q.rho * q.v;
+                        out[3] = q.rho * q.w;
+                        out[4] = (pref + q.pd) / gm1 + 0.5 * q.rho * (q.u * q.u + q.v * q.v + q.w * q.w);
+                    };
+                    double Uo[5], Un[5];
+                    cons(qf, Uo);
+                    cons(qn, Un);
+                    llf_add(qf, qn, Uo, Un, nx, ny, nz, gamma, pref, F);
+                } else if (A.diss == 2) {
+                    roe_add(qf, qn, nx, ny, nz, gamma, pref, F);
+                }
+#pragma unroll
+                for (int s = 0; s < 5; ++s) RF[(f * 5 + s) * Q2 + l] = (rf[s] + F[s]) * wperp;
+            }
         }
-        __syncthreads();
-    }
-    if (active) {
-#pragma unroll
-        for (int side = 0; side < 2; ++side)
-#pragma unroll
-            for (int s = 0; s < 5; ++s) RF[((2 * dir + side) * 5 + s) * Q2 + l] = Rf[side][s] * wperp;
+        accumulate(Rv, false);
     }
     // manufactured source at the volume points: R -= W J q
     const int mode = A.mode;
@@ -724,19 +738,63 @@ __global__ __launch_bounds__(DG_BLOCK) void dg_stage_kernel(StageArgs A, GLArgs 
     const int base = dir == 0 ? Q * t1 + Q2 * t2 : (dir == 1 ? t1 + Q2 * t2 : t1 + Q * t2);
     const int stride = dir == 0 ? 1 : (dir == 1 ? Q : Q2);
     double* va = VA + (active ? el : 0) * 5 * Q3;
-    double Rv[5][Q], Rf[2][5];
+    const double wperp = mw[t1] * mw[t2];
+    // (a) the flux-basis derivative along the line and the line's end values of
+    //     f^r_k; the volume part into VA in a fixed direction order
+    double Rf[2][5];
+    {
+        double Rv[5][Q];
 #pragma unroll
-    for (int s = 0; s < 5; ++s) {
+        for (int s = 0; s < 5; ++s) {
 #pragma unroll
-        for (int a = 0; a < Q; ++a) Rv[s][a] = 0.0;
-        Rf[0][s] = Rf[1][s] = 0.0;
+            for (int a = 0; a < Q; ++a) Rv[s][a] = 0.0;
+            Rf[0][s] = Rf[1][s] = 0.0;
+        }
+        if (active) {
+            const double* Cl = G.geo.Cq + (int64_t)(3 * dir) * E * Q3 + e * Q3 + l;
+            const int64_t CS = E * Q3;
+#pragma unroll
+            for (int b = 0; b < Q; ++b) {
+                const int t = base + b * stride;
+                const double r = va[t], m1 = va[Q3 + t], m2 = va[2 * Q3 + t], m3 = va[3 * Q3 + t],
+                             en = va[4 * Q3 + t];
+                const double cx = Cl[b * Q2], cy = Cl[CS + b * Q2], cz = Cl[2 * CS + b * Q2];
+                const double ir = 1.0 / r;
+                const double unb = (m1 * cx + m2 * cy + m3 * cz) * ir;
+                const double p = gm1 * (en - 0.5 * (m1 * m1 + m2 * m2 + m3 * m3) * ir);
+                const double pd = p - pref;
+                const double fr[5] = {r * unb, m1 * unb + pd * cx, m2 * unb + pd * cy, m3 * unb + pd * cz,
+                                      (en + p) * unb};
+#pragma unroll
+                for (int s = 0; s < 5; ++s) {
+#pragma unroll
+                    for (int a = 0; a < Q; ++a) Rv[s][a] = __builtin_fma(mdq[a * Q + b], fr[s], Rv[s][a]);
+                    Rf[0][s] = __builtin_fma(mtl[b], fr[s], Rf[0][s]);
+                    Rf[1][s] = __builtin_fma(mtr[b], fr[s], Rf[1][s]);
+                }
+            }
+        }
+        __syncthreads();   // the volume states (VA) are no longer read
+        for (int ph = 0; ph < 3; ++ph) {
+            if (active && dir == ph) {
+#pragma unroll
+                for (int s = 0; s < 5; ++s)
+#pragma unroll
+                    for (int a = 0; a < Q; ++a) {
+                        const double v = Rv[s][a] * (mw[a] * wperp);
+                        double* x = va + s * Q3 + base + a * stride;
+                        if (ph == 0) *x = v;
+                        else *x += v;
+                    }
+            }
+            __syncthreads();
+        }
     }
+    // (b) the face terms at both ends, N . f* - s t . f^r (s = -1 left, +1
+    //     right), with Roe's flux against the neighbour's face state
     if (active) {
-        const double* Cl = G.geo.Cq + (int64_t)(3 * dir) * E * Q3 + e * Q3 + l;
-        const int64_t CS = E * Q3;
         const int64_t FS = E * Q2;
-        // face operands first: their latency overlaps the volume work
-        double uo[2][5], un[2][5], nxs[2], nys[2], nzs[2];
+        double* rf = RF + el * 30 * Q2;
 #pragma unroll
         for (int side = 0; side < 2; ++side) {
             const int f = 2 * dir + side;
@@ -745,65 +803,18 @@ __global__ __launch_bounds__(DG_BLOCK) void dg_stage_kernel(StageArgs A, GLArgs 
             const int en = A.geo.nbr[(int64_t)f * E + e];
             const int fn = 2 * dir + (1 - side);
             const double* Cfn = G.geo.Cf + ((int64_t)(fn * 3) * E + en) * Q2 + l;
-            nxs[side] = 0.5 * sg * (Cfo[0] + Cfn[0]);
-            nys[side] = 0.5 * sg * (Cfo[FS] + Cfn[FS]);
-            nzs[side] = 0.5 * sg * (Cfo[2 * FS] + Cfn[2 * FS]);
+            const double nx = 0.5 * sg * (Cfo[0] + Cfn[0]), ny = 0.5 * sg * (Cfo[FS] + Cfn[FS]),
+                         nz = 0.5 * sg * (Cfo[2 * FS] + Cfn[2 * FS]);
+            double uo[5], un[5], F[5];
 #pragma unroll
             for (int s = 0; s < 5; ++s) {
-                uo[side][s] = G.ft[((int64_t)(f * 5 + s) * E + e) * Q2 + l];
-                un[side][s] = G.ft[((int64_t)(fn * 5 + s) * E + en) * Q2 + l];
+                uo[s] = G.ft[((int64_t)(f * 5 + s) * E + e) * Q2 + l];
+                un[s] = G.ft[((int64_t)(fn * 5 + s) * E + en) * Q2 + l];
             }
+            roe_flux_dev(uo, un, nx, ny, nz, gamma, pref, F);
+#pragma unroll
+            for (int s = 0; s < 5; ++s) rf[(f * 5 + s) * Q2 + l] = (F[s] - sg * Rf[side][s]) * wperp;
         }
-#pragma unroll
-        for (int b = 0; b < Q; ++b) {
-            const int t = base + b * stride;
-            const double r = va[t], m1 = va[Q3 + t], m2 = va[2 * Q3 + t], m3 = va[3 * Q3 + t], en = va[4 * Q3 + t];
-            const double cx = Cl[b * Q2], cy = Cl[CS + b * Q2], cz = Cl[2 * CS + b * Q2];
-            const double ir = 1.0 / r;
-            const double unb = (m1 * cx + m2 * cy + m3 * cz) * ir;
-            const double p = gm1 * (en - 0.5 * (m1 * m1 + m2 * m2 + m3 * m3) * ir);
-            const double pd = p - pref;
-            const double fr[5] = {r * unb, m1 * unb + pd * cx, m2 * unb + pd * cy, m3 * unb + pd * cz, (en + p) * unb};
-#pragma unroll
-            for (int s = 0; s < 5; ++s) {
-#pragma unroll
-                for (int a = 0; a < Q; ++a) Rv[s][a] = __builtin_fma(mdq[a * Q + b], fr[s], Rv[s][a]);
-                Rf[0][s] = __builtin_fma(mtl[b], fr[s], Rf[0][s]);
-                Rf[1][s] = __builtin_fma(mtr[b], fr[s], Rf[1][s]);
-            }
-        }
-        // face terms: N . f* - s t . f^r (s = -1 at the left end, +1 at the right)
-#pragma unroll
-        for (int side = 0; side < 2; ++side) {
-            const double sg = side ? 1.0 : -1.0;
-            double F[5];
-            roe_flux_dev(uo[side], un[side], nxs[side], nys[side], nzs[side], gamma, pref, F);
-#pragma unroll
-            for (int s = 0; s < 5; ++s) Rf[side][s] = F[s] - sg * Rf[side][s];
-        }
-    }
-    __syncthreads();   // the volume states (VA) are no longer read
-    const double wperp = mw[t1] * mw[t2];
-    for (int ph = 0; ph < 3; ++ph) {
-        if (active && dir == ph) {
-#pragma unroll
-            for (int s = 0; s < 5; ++s)
-#pragma unroll
-                for (int a = 0; a < Q; ++a) {
-                    const double v = Rv[s][a] * (mw[a] * wperp);
-                    double* x = va + s * Q3 + base + a * stride;
-                    if (ph == 0) *x = v;
-                    else *x += v;
-                }
-        }
-        __syncthreads();
-    }
-    if (active) {
-        double* rf = RF + el * 30 * Q2;
-#pragma unroll
-        for (int side = 0; side < 2; ++side)
-#pragma unroll
-            for (int s = 0; s < 5; ++s) rf[((2 * dir + side) * 5 + s) * Q2 + l] = Rf[side][s] * wperp;
     }
     const int mode = A.mode;
     double dt = 0.0, cstage = 0.0;
