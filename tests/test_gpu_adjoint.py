@@ -60,6 +60,20 @@ def test_vjp_dot_product_full_size(lib):
     assert abs(float(fd - an)) < 1e-6 * abs(float(an))
 
 
+def test_vjp_parity_full_size_24(lib):
+    """Adjoint workload, 24^3 warped TGV, p = 4, c = c_HU, every element: the
+    GPU VJP against the oracle's reverse-mode VJP of its own rhs, with a random
+    lambda (no cancellation in the result, so the plain 1e-12 bar)."""
+    from paper_2312_07725_amd.nsfr import NSFR
+    c = oracle.operators.c_hu(4)
+    g = NSFR(4, 24, beta=0.2, c=c)
+    o = oracle.Scheme(4, (24, 24, 24), beta=0.2, c=c)
+    U = inputs.tgv_state(o.X)
+    lam = inputs.normal_like(U.shape, 1)
+    got = g.rhs_vjp(cuda(U), cuda(lam))
+    assert_parity(got, oadj.vjp(o, U, lam), 1e-12, "vjp 24^3 p=4")
+
+
 @pytest.mark.parametrize("c", ["0", "chu"])
 def test_rk4_step_vjp_parity(c, lib):
     p = 3
