@@ -307,8 +307,8 @@ class Ensemble:
         _check(_lib().nsfr_ens_create(arr, len(self.configs), _stream(), byref(self._h)), "nsfr_ens_create")
         offs = (c_int64 * (len(self.configs) + 1))()
         _check(_lib().nsfr_ens_offsets(self._h, offs), "nsfr_ens_offsets")
-        from .tune import load_tiles
-        for p, epb in load_tiles().items():
+        from .tune import load_ensemble_tiles
+        for p, epb in load_ensemble_tiles().items():
             if _lib().nsfr_ens_set_tile(self._h, int(p), int(epb)) != NSFR_OK:
                 _lib().nsfr_ens_set_tile(self._h, int(p), 0)
         self.offsets = [int(v) for v in offs]

@@ -1,12 +1,20 @@
 """Autotuner for the stage-kernel tile (elements per workgroup) per degree.
 
     python -m paper_2312_07725_amd.tune [--ne 16] [--reps 200] [--out PATH]
+    python -m paper_2312_07725_amd.tune --ensemble [--reps 50] [--out PATH]
 
 For every p in 2..5 it times the full right-hand side (nsfr_rhs: volume and
 surface fluxes, weight-adjusted inverse with c = c_HU) of the warped TGV on an
 ne^3 mesh for every tile the library accepts, and writes the fastest tile per
 degree to tiles_gfx950.json next to this file. NSFR(tile=0) and Ensemble read
 that table. Timing uses HIP events on the current stream, median of 5 batches.
+
+With --ensemble it tunes the tiles the ensemble kernels use instead, on the
+ensemble itself (64 TGV flows, seed 0, mixed degrees and mesh sizes): for each
+degree in turn, every tile is timed with the other degrees' tiles held, and
+the fastest is kept (one coordinate sweep). The result is stored as
+"ensemble_tiles" next to the single-flow "tiles" of the same file; Ensemble
+reads it (falling back to "tiles").
 """
 import argparse
 import json
@@ -28,6 +36,57 @@ def load_tiles(path=TILES_PATH):
         return {int(k): int(v["epb"]) for k, v in d.get("tiles", {}).items()}
     except (OSError, ValueError, KeyError):
         return {}
+
+
+def load_ensemble_tiles(path=TILES_PATH):
+    """{p: epb} tuned on the ensemble, else the single-flow table."""
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+        t = d.get("ensemble_tiles")
+        if t:
+            return {int(k): int(v["epb"]) for k, v in t.items()}
+    except (OSError, ValueError, KeyError):
+        pass
+    return load_tiles(path)
+
+
+def tune_ensemble(reps=50, out=TILES_PATH, base=TILES_PATH, verbose=True):
+    from . import inputs
+    from .nsfr import Ensemble, NSFR, NSFRError, c_hu, make_config
+    draws = inputs.ensemble_draws(64, seed=0)
+    ens = Ensemble([make_config(p, ne, beta=0.2, c=c_hu(p)) for (ne, p, m) in draws])
+    U = ens.empty()
+    for i, (ne, p, mach) in enumerate(draws):
+        g = NSFR(p, ne, beta=0.2, c=c_hu(p))
+        ens.flow_view(U, i).copy_(inputs.tgv_state(g.node_coords().cpu(), 1.4, mach))
+        del g
+    out_t = ens.empty()
+    table = {}
+    for p in sorted({p for (_, p, _) in draws}):
+        res = {}
+        for epb in range(1, 33):
+            try:
+                ens.set_tile(p, epb)
+            except NSFRError:
+                continue
+            res[epb] = time_rhs(ens, U, out_t, reps)
+            if verbose:
+                print(f"ensemble p={p} epb={epb}: {res[epb]:.2f} us", flush=True)
+        best = min(res, key=res.get)
+        ens.set_tile(p, best)
+        table[str(p)] = {"epb": best, "rhs_us": res[best], "all_us": {str(k): v for k, v in res.items()}}
+    try:
+        with open(base) as fh:
+            doc = json.load(fh)
+    except (OSError, ValueError):
+        doc = {}
+    doc["ensemble_tiles"] = table
+    doc["ensemble"] = "64 TGV flows (inputs.ensemble_draws(64, seed=0)), c=c_HU; time of one ensemble rhs (us)"
+    if out:
+        with open(out, "w") as fh:
+            json.dump(doc, fh, indent=1)
+    return doc
 
 
 def time_rhs(g, U, out, reps):
@@ -82,9 +141,14 @@ def main():
     ap.add_argument("--ne", type=int, default=16)
     ap.add_argument("--reps", type=int, default=200)
     ap.add_argument("--out", default=TILES_PATH)
+    ap.add_argument("--ensemble", action="store_true", help="tune the ensemble kernels' tiles on the ensemble")
     a = ap.parse_args()
-    doc = tune(a.ne, a.reps, out=a.out)
-    json.dump({k: v["epb"] for k, v in doc["tiles"].items()}, sys.stdout)
+    if a.ensemble:
+        doc = tune_ensemble(a.reps, out=a.out)
+        json.dump({k: v["epb"] for k, v in doc["ensemble_tiles"].items()}, sys.stdout)
+    else:
+        doc = tune(a.ne, a.reps, out=a.out)
+        json.dump({k: v["epb"] for k, v in doc["tiles"].items()}, sys.stdout)
     print()
 
 
