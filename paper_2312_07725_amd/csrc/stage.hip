@@ -15,36 +15,95 @@
 // (p+1) p / 2 node pairs are evaluated once each (pair symmetry), and the two
 // endpoint face fluxes of the line are computed by the same thread, so every
 // face node's surface term belongs to exactly one thread (no atomics; the
-// kernel is deterministic). Partial residuals of the three directions are
-// summed in LDS in a fixed order, then the weight-adjusted inverse and the RK
-// combination run node-parallel.
+// kernel is deterministic). The partial residuals of the three directions go
+// to three LDS slots and are summed in a fixed order by the first pass of the
+// weight-adjusted inverse (plane and zeta-line passes); the RK combination
+// runs node-parallel.
 #include "nsfr_host.h"
 
 namespace nsfr {
 
 constexpr int STAGE_BLOCK_MAX = 512;
 
-// One pass of a rank-one line operator x <- x - vec (coef . x) along
-// direction dir for all (element, state, line) of the workgroup, in the LDS
-// accumulator [epb][5][PN3] (padded node index).
+// Accumulator layout after the line sweep: per element three slots (one per
+// line direction) of [5][PN3] (padded node index), EBLK = 3 SLOT doubles per
+// element.
+//
+// The weight-adjusted inverse Pi~ (W J)^-1 Pi~^T with Pi~ = P (x) P (x) P,
+// P = I - pia pib^T applied along a line as x <- x - pia (pib . x) (and P^T
+// as x <- x - pib (pia . x)). The three 1D factors act on different indices
+// and commute, so the operator is applied as P_xi P_eta [P_zeta (W J)^-1
+// P_zeta^T] P_xi^T P_eta^T: a plane pass, a zeta-line pass that also scales,
+// and a plane pass (three barriers instead of seven).
+
+// Rank-one operator along xi and along eta on every (element, state,
+// zeta-plane) of the workgroup: w <- w - vec (coef . w) on each xi-row, then
+// on each eta-column. With SUM the input is the sum of the three direction
+// slots (fixed order) and the result goes to slot 0.
+template <int N, int PN3, bool SUM>
+__device__ __forceinline__ void plane_pass(double* lr, int epb, const double* coef, const double* vec) {
+    constexpr int N2 = N * N, SLOT = 5 * PN3, EBLK = 3 * SLOT;
+    for (int it = threadIdx.x; it < epb * 5 * N; it += blockDim.x) {
+        const int k = it % N, sl = it / N;   // zeta plane; element * 5 + state
+        const int eli = sl / 5, st = sl - eli * 5;
+        double* x = lr + eli * EBLK + st * PN3;
+        double w[N][N];   // [eta][xi]
+#pragma unroll
+        for (int j = 0; j < N; ++j)
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                const int pn = pad_node<N>(i + N * j + N2 * k);
+                w[j][i] = SUM ? (x[pn] + x[SLOT + pn]) + x[2 * SLOT + pn] : x[pn];
+            }
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            double t = 0.0;
+#pragma unroll
+            for (int i = 0; i < N; ++i) t += coef[i] * w[j][i];
+#pragma unroll
+            for (int i = 0; i < N; ++i) w[j][i] = w[j][i] - vec[i] * t;
+        }
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            double t = 0.0;
+#pragma unroll
+            for (int j = 0; j < N; ++j) t += coef[j] * w[j][i];
+#pragma unroll
+            for (int j = 0; j < N; ++j) w[j][i] = w[j][i] - vec[j] * t;
+        }
+#pragma unroll
+        for (int j = 0; j < N; ++j)
+#pragma unroll
+            for (int i = 0; i < N; ++i) x[pad_node<N>(i + N * j + N2 * k)] = w[j][i];
+    }
+}
+
+// P^T, the scaling by 1/(W J) at the line's nodes (iw, prefetched by the
+// caller) and P along the zeta-line of thread `item` (= element * N^2 + line
+// when below epb N^2), all five states, in slot 0.
 template <int N, int PN3>
-__device__ __forceinline__ void line_pass(double* lr, int epb, int dir, const double* coef, const double* vec) {
-    constexpr int N2 = N * N;
-    for (int it = threadIdx.x; it < epb * 5 * N2; it += blockDim.x) {
-        int l = it % N2;
-        int sl = it / N2;   // element * 5 + state
-        int base, stride;
-        line_geometry<N>(dir, l, base, stride);
-        double* x = lr + sl * PN3;
+__device__ __forceinline__ void zeta_pass(double* lr, int item, int epb, const double iw[N], const double* pia,
+                                          const double* pib) {
+    constexpr int N2 = N * N, SLOT = 5 * PN3, EBLK = 3 * SLOT;
+    if (item >= epb * N2) return;
+    const int eli = item / N2, l = item - eli * N2;   // zeta line: base l, stride N^2
+#pragma unroll
+    for (int st = 0; st < 5; ++st) {
+        double* x = lr + eli * EBLK + st * PN3;
         double v[N];
         double t = 0.0;
 #pragma unroll
         for (int a = 0; a < N; ++a) {
-            v[a] = x[pad_node<N>(base + a * stride)];
-            t += coef[a] * v[a];
+            v[a] = x[pad_node<N>(l + a * N2)];
+            t += pia[a] * v[a];
         }
 #pragma unroll
-        for (int a = 0; a < N; ++a) x[pad_node<N>(base + a * stride)] = v[a] - vec[a] * t;
+        for (int a = 0; a < N; ++a) v[a] = (v[a] - pib[a] * t) * iw[a];
+        t = 0.0;
+#pragma unroll
+        for (int a = 0; a < N; ++a) t += pib[a] * v[a];
+#pragma unroll
+        for (int a = 0; a < N; ++a) x[pad_node<N>(l + a * N2)] = v[a] - pia[a] * t;
     }
 }
 
@@ -58,16 +117,25 @@ __device__ __forceinline__ void line_pass(double* lr, int epb, int dir, const do
 // the column in registers is slightly faster and saves the LDS.
 __host__ __device__ constexpr bool metric_in_lds(int p) { return p == 3; }
 
-// LDS per element: the primitives [6][N3] (padded), and at p = 3 the metric
-// columns; after the pair sweep the primitive block is reused for the
-// residual accumulator [5][N3]. A line thread keeps its residual in registers
-// and reads the primitives from LDS inside the pair loop.
+// LDS per element (doubles): during the sweep the primitives [6][PN3]
+// (padded) and at p = 3 the metric columns [9][N3]; afterwards the three
+// direction slots [3][5][PN3] of the accumulator.
+__host__ __device__ constexpr int stage_lds_per_elem(int n) {
+    const int sweep = 6 * (n * n * n + n * n) + (metric_in_lds(n - 1) ? 9 * n * n * n : 0);
+    const int acc = 15 * (n * n * n + n * n);
+    return sweep > acc ? sweep : acc;
+}
+
+// A line thread keeps its residual in registers and reads the primitives
+// from LDS inside the pair loop; after the sweep the LDS holds the direction
+// slots of the accumulator.
 template <int P, bool CWA, int VARIANT, int DISS>
 __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0, double* lds) {
     constexpr int N = P + 1, N2 = N * N, N3 = N2 * N, LINES = 3 * N2;
     constexpr int PN3 = padded_block<N>();          // padded stride of a primitive component
     constexpr bool MLDS = metric_in_lds(P);
-    constexpr int LDSE = 6 * PN3 + (MLDS ? 9 * N3 : 0);   // LDS doubles per element
+    constexpr int SLOT = 5 * PN3, EBLK = 3 * SLOT;    // direction slots of the accumulator
+    constexpr int LDSE = stage_lds_per_elem(N);         // LDS doubles per element
     const int tid = threadIdx.x, nth = blockDim.x;
     const int epb = A.epb;
     const int64_t E = A.geo.E;
@@ -96,6 +164,32 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
             for (int a = 0; a < N; ++a) cl[m][a] = Cg[(int64_t)m * SE + a * N2];
     }
 
+    // line geometry, and the traces of the two face neighbours across the
+    // line's ends (periodic box): conserved state and metric column at the
+    // neighbour's end node (and, with local Lax-Friedrichs, the own conserved
+    // state). Requested before the staging so that their latency overlaps it.
+    int base, stride;
+    line_geometry<N>(dir, l, base, stride);
+    double fU[2][5], fC[2][3], oU[2][5];
+    if (active) {
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const int anbr = side ? 0 : N - 1;
+            const int64_t en = neighbour((int)e, dir, side ? 1 : -1, A.geo.nx, A.geo.ny, A.geo.nz);
+            const double* Cn = A.geo.Cline + ((int64_t)(dir * 3) * E + en) * N3 + anbr * N2 + l;
+            const double* Ub = A.Uin + en * N3 + base + anbr * stride;
+#pragma unroll
+            for (int s = 0; s < 5; ++s) fU[side][s] = Ub[s * SE];
+#pragma unroll
+            for (int m = 0; m < 3; ++m) fC[side][m] = Cn[m * SE];
+            if (DISS == 1) {
+                const double* Uo = A.Uin + e * N3 + base + (side ? N - 1 : 0) * stride;
+#pragma unroll
+                for (int s = 0; s < 5; ++s) oU[side][s] = Uo[s * SE];
+            }
+        }
+    }
+
     // ---- 1. primitives (and at p = 3 the metric columns) of the workgroup's elements -> LDS
     for (int idx = tid; idx < epb * N3; idx += nth) {
         const int eli = idx / N3, node = idx - eli * N3;
@@ -120,20 +214,35 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
     }
     __syncthreads();
 
-    // ---- 2. line geometry
-    int base, stride;
-    line_geometry<N>(dir, l, base, stride);
+    // ---- 2. the line's views of LDS
     const double* Lp = lds + el * LDSE;                             // primitives
     const double* Lc = lds + el * LDSE + 6 * PN3 + 3 * dir * N3 + l;   // [comp][position][line] (p = 3)
     auto cmet = [&](int m, int a) { return MLDS ? Lc[m * N3 + a * N2] : cl[m][a]; };
 
-    // ---- 3. line residual: volume pairs, then the two endpoint face fluxes
+    // ---- 3. line residual: the two endpoint face fluxes, then the volume pairs
     double R[5][N];
 #pragma unroll
     for (int s = 0; s < 5; ++s)
 #pragma unroll
         for (int a = 0; a < N; ++a) R[s][a] = 0.0;
     if (active) {
+        // the two endpoint face fluxes (own trace against the neighbour's)
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const int aown = side ? N - 1 : 0;
+            const double sg = side ? 0.5 : -0.5;   // outward reference normal / 2
+            const PrimR qn = primitives_ref(fU[side][0], fU[side][1], fU[side][2], fU[side][3], fU[side][4], gm1, pref);
+            const PrimR qo = lds_primr<PN3>(Lp, pad_node<N>(base + aown * stride));
+            const double nx = sg * (cmet(0, aown) + fC[side][0]), ny = sg * (cmet(1, aown) + fC[side][1]),
+                         nz = sg * (cmet(2, aown) + fC[side][2]);
+            double F[5];
+            ec_flux<VARIANT>(qo, qn, nx, ny, nz, c1, pref, F);
+            if (DISS == 1) llf_add(qo, qn, oU[side], fU[side], nx, ny, nz, A.gamma, pref, F);
+            else if (DISS == 2) roe_add(qo, qn, nx, ny, nz, A.gamma, pref, F);
+#pragma unroll
+            for (int s = 0; s < 5; ++s) R[s][aown] += F[s];
+        }
+        // volume pairs of the line
 #pragma unroll
         for (int a = 0; a < N - 1; ++a) {
             const PrimR qa = lds_primr<PN3>(Lp, pad_node<N>(base + a * stride));
@@ -153,44 +262,14 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
                 }
             }
         }
-        // face neighbours across the two ends of this line (periodic box)
-#pragma unroll
-        for (int side = 0; side < 2; ++side) {
-            const int aown = side ? N - 1 : 0;
-            const double sg = side ? 0.5 : -0.5;   // outward reference normal / 2
-            const int anbr = side ? 0 : N - 1;
-            const int64_t en = A.geo.nbr[(int64_t)(2 * dir + side) * E + e];
-            const double* Cn = A.geo.Cline + ((int64_t)(dir * 3) * E + en) * N3 + anbr * N2 + l;
-            const double* Ub = A.Uin + en * N3 + base + anbr * stride;
-            double Un5[5];
-#pragma unroll
-            for (int s = 0; s < 5; ++s) Un5[s] = Ub[s * SE];
-            const double cnx = Cn[0], cny = Cn[SE], cnz = Cn[2 * SE];
-            const PrimR qn = primitives_ref(Un5[0], Un5[1], Un5[2], Un5[3], Un5[4], gm1, pref);
-            const PrimR qo = lds_primr<PN3>(Lp, pad_node<N>(base + aown * stride));
-            const double nx = sg * (cmet(0, aown) + cnx), ny = sg * (cmet(1, aown) + cny),
-                         nz = sg * (cmet(2, aown) + cnz);
-            double F[5];
-            ec_flux<VARIANT>(qo, qn, nx, ny, nz, c1, pref, F);
-            if (DISS == 1) {
-                const double* Uo = A.Uin + e * N3 + base + aown * stride;
-                double Uo5[5];
-#pragma unroll
-                for (int s = 0; s < 5; ++s) Uo5[s] = Uo[s * SE];
-                llf_add(qo, qn, Uo5, Un5, nx, ny, nz, A.gamma, pref, F);
-            } else if (DISS == 2) {
-                roe_add(qo, qn, nx, ny, nz, A.gamma, pref, F);
-            }
-#pragma unroll
-            for (int s = 0; s < 5; ++s) R[s][aown] += F[s];
-        }
     }
     // The node-parallel epilogue gives thread tid the nodes tid + j * nth,
-    // j < KP (nth >= epb * 3 N^2). Request their global operands now, so that
-    // the latency overlaps the LDS reduction and the mass-inverse passes.
+    // j < KP (nth >= epb * 3 N^2); with the weight-adjusted inverse the thread
+    // also scales the zeta-line `tid` (when tid < epb N^2). Request their
+    // global operands now, so that the latency overlaps the LDS passes.
     constexpr int KP = (N + 2) / 3;
     const int mode = A.mode;
-    double pf_iw[KP], pf_a[KP][5], pf_b[KP][5];
+    double pf_iw[KP], pf_a[KP][5], pf_b[KP][5], zw[N];
     auto fetch_epilogue = [&]() {
 #pragma unroll
         for (int j = 0; j < KP; ++j) {
@@ -202,7 +281,7 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
             for (int s = 0; s < 5; ++s) pf_a[j][s] = pf_b[j][s] = 0.0;
             if (idx < epb * N3 && ee < E && mode != MODE_RESIDUAL) {
                 const int64_t g = ee * N3 + node;
-                pf_iw[j] = A.geo.invWJ[g];
+                if (!CWA) pf_iw[j] = A.geo.invWJ[g];
                 const double* pa = mode == MODE_RK1 ? A.Uin : A.acc;
 #pragma unroll
                 for (int s = 0; s < 5; ++s) {
@@ -211,29 +290,38 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
                 }
             }
         }
+#pragma unroll
+        for (int a = 0; a < N; ++a) zw[a] = 0.0;
+        if (CWA && mode != MODE_RESIDUAL && tid < epb * N2) {
+            const int eli = tid / N2, zl = tid - eli * N2;
+            if (e0 + eli < E) {
+                const double* iw = A.geo.invWJ + (e0 + eli) * N3 + zl;
+#pragma unroll
+                for (int a = 0; a < N; ++a) zw[a] = iw[a * N2];
+            }
+        }
     };
     fetch_epilogue();
-    __syncthreads();   // all LDS line reads are done; the primitive block becomes the accumulator
+    __syncthreads();   // all LDS line reads are done; the LDS becomes the accumulator
 
-    // ---- 4. sum the three directions in LDS ([epb][5][N3] at the element's
-    //         block start), fixed order
+    // ---- 4. every line thread stores its residual, weighted by the
+    //         tangential quadrature weights, in its direction's slot (one
+    //         store per value, no read-modify-write)
     double* lr = lds;
-    const double wperp = A.ops.w[l % N] * A.ops.w[l / N];
-    for (int ph = 0; ph < 3; ++ph) {
-        if (active && dir == ph) {
-            double* x = lr + el * 5 * PN3;
+    if (active) {
+        const double wperp = A.ops.w[l % N] * A.ops.w[l / N];
+        double* x = lr + el * EBLK + dir * SLOT;
 #pragma unroll
-            for (int s = 0; s < 5; ++s)
+        for (int s = 0; s < 5; ++s)
 #pragma unroll
-                for (int a = 0; a < N; ++a) {
-                    const double v = R[s][a] * wperp;
-                    const int pn = s * PN3 + pad_node<N>(base + a * stride);
-                    if (ph == 0) x[pn] = v;
-                    else x[pn] += v;
-                }
-        }
-        __syncthreads();
+            for (int a = 0; a < N; ++a) x[s * PN3 + pad_node<N>(base + a * stride)] = R[s][a] * wperp;
     }
+    __syncthreads();
+    // residual of (element, state, node): the three directions summed in a fixed order
+    auto rsum = [&](int eli, int s, int node) {
+        const double* x = lr + eli * EBLK + s * PN3 + pad_node<N>(node);
+        return (x[0] + x[SLOT]) + x[2 * SLOT];
+    };
 
     // ---- 5. source, mass inverse, RK combination (node-parallel)
     double dt = 0.0, cstage = 0.0;
@@ -251,7 +339,7 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
                 const double* X = A.geo.X + ee * N3 + node;
                 mms_source(X[0], X[SE], X[2 * SE], t, A.gamma, qs);
                 double wj = 1.0 / A.geo.invWJ[ee * N3 + node];
-                double* x = lr + eli * 5 * PN3 + pad_node<N>(node);
+                double* x = lr + eli * EBLK + pad_node<N>(node);   // slot 0
 #pragma unroll
                 for (int s = 0; s < 5; ++s) x[s * PN3] -= wj * qs[s];
             }
@@ -265,30 +353,18 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
             if (ee < E) {
 #pragma unroll
                 for (int s = 0; s < 5; ++s)
-                    A.out[s * SE + ee * N3 + node] = lr[(eli * 5 + s) * PN3 + pad_node<N>(node)];
+                    A.out[s * SE + ee * N3 + node] = rsum(eli, s, node);
             }
         }
         return;
     }
     if (CWA) {
-        for (int d = 0; d < 3; ++d) {   // Pi~^T along xi, eta, zeta
-            line_pass<N, PN3>(lr, epb, d, A.ops.pia, A.ops.pib);
-            __syncthreads();
-        }
-#pragma unroll
-        for (int j = 0; j < KP; ++j) {
-            const int idx = tid + j * nth;
-            if (idx < epb * N3) {
-                const int eli = idx / N3, node = idx - eli * N3;
-#pragma unroll
-                for (int s = 0; s < 5; ++s) lr[(eli * 5 + s) * PN3 + pad_node<N>(node)] *= pf_iw[j];
-            }
-        }
+        plane_pass<N, PN3, true>(lr, epb, A.ops.pia, A.ops.pib);   // sum of the slots, P^T along xi, eta
         __syncthreads();
-        for (int d = 0; d < 3; ++d) {   // Pi~ along xi, eta, zeta
-            line_pass<N, PN3>(lr, epb, d, A.ops.pib, A.ops.pia);
-            __syncthreads();
-        }
+        zeta_pass<N, PN3>(lr, tid, epb, zw, A.ops.pia, A.ops.pib);   // P^T, 1/(W J), P along zeta
+        __syncthreads();
+        plane_pass<N, PN3, false>(lr, epb, A.ops.pib, A.ops.pia);   // P along xi, eta
+        __syncthreads();
     }
 #pragma unroll
     for (int j = 0; j < KP; ++j) {
@@ -297,10 +373,9 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
         const int64_t ee = e0 + eli;
         if (idx >= epb * N3 || ee >= E) continue;
         const int64_t g = ee * N3 + node;
-        const double iw = CWA ? 1.0 : pf_iw[j];
 #pragma unroll
         for (int s = 0; s < 5; ++s) {
-            const double k = -(lr[(eli * 5 + s) * PN3 + pad_node<N>(node)] * iw);
+            const double k = CWA ? -lr[eli * EBLK + s * PN3 + pad_node<N>(node)] : -(rsum(eli, s, node) * pf_iw[j]);
             const int64_t gi = s * SE + g;
             switch (mode) {
                 case MODE_RHS: A.out[gi] = k; break;
@@ -362,8 +437,7 @@ static hipError_t launch_kind_t(const StageArgs* table, const int2* items, int n
     return hipGetLastError();
 }
 
-// LDS per element of the stage kernel (doubles): primitives (padded) + metric columns
-static int stage_lds_doubles(int n) { return 6 * (n * n * n + n * n) + (metric_in_lds(n - 1) ? 9 * n * n * n : 0); }
+static int stage_lds_doubles(int n) { return stage_lds_per_elem(n); }
 
 size_t stage_lds_bytes(int p, int epb) { return (size_t)epb * stage_lds_doubles(p + 1) * sizeof(double); }
 
