@@ -75,8 +75,13 @@ struct PrimR {
     double rho, u, v, w, pd, beta;
 };
 
+// Every operation is rounded as written (no FMA contraction): the kernels
+// evaluate this at several sites (staging, face traces) and rely on getting
+// the same bits for the same state, and the Fast2Sum of E - kin is exact only
+// when kin is the same rounded value in both of its uses.
 __device__ __forceinline__ PrimR primitives_ref(double r, double m1, double m2, double m3, double E, double gm1,
                                                 double pref) {
+#pragma clang fp contract(off)
     PrimR q;
     double ir = rcp_pos(r);
     q.rho = r;

@@ -163,6 +163,29 @@ def test_tiles_and_determinism(lib):
 
 
 @pytest.mark.parametrize("p", [2, 3, 4, 5])
+def test_library_default_tile(p, lib):
+    """tile = 0 passed straight through the C ABI (the library's own default,
+    not the binding's tuned tile) runs and gives the result of tile 1."""
+    from ctypes import byref, c_void_p
+    from paper_2312_07725_amd import nsfr
+    o = oracle.Scheme(p, (3, 5, 2), beta=0.2, c=1e-3)
+    U = cuda(state(o, "rough", seed=6))
+    ref = nsfr.NSFR(p, (3, 5, 2), beta=0.2, c=1e-3, tile=1).rhs(U)
+    L = nsfr._lib()
+    cfg = nsfr.make_config(p, (3, 5, 2), beta=0.2, c=1e-3, tile=0)
+    h = c_void_p()
+    assert L.nsfr_create(byref(cfg), c_void_p(torch.cuda.current_stream().cuda_stream), byref(h)) == 0
+    try:
+        out = torch.empty_like(U)
+        st = L.nsfr_rhs(h, c_void_p(U.data_ptr()), c_void_p(out.data_ptr()), 0.0)
+        assert st == 0, L.nsfr_last_error()
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref)
+    finally:
+        L.nsfr_destroy(h)
+
+
+@pytest.mark.parametrize("p", [2, 3, 4, 5])
 def test_invariants_on_gpu(p, lib):
     """Sec. 6.1-6.3: free-stream preservation, global conservation and entropy
     conservation of the GPU residual on the warped periodic mesh."""
