@@ -78,17 +78,21 @@ __device__ __forceinline__ void plane_pass(double* lr, int epb, const double* co
     }
 }
 
-// P^T, the scaling by 1/(W J) at the line's nodes (iw, prefetched by the
-// caller) and P along the zeta-line of thread `item` (= element * N^2 + line
-// when below epb N^2), all five states, in slot 0.
+// P^T, the scaling by 1/(W J) at the line's nodes and P along zeta-lines,
+// in slot 0. The epb * 5 * N^2 (element, state, line) items go to the
+// threads as item tid + j * nth, j < 2 (nth >= epb * 3 N^2 covers them in
+// two rounds); iw[j] holds 1/(W J) at item j's nodes, prefetched by the
+// caller.
 template <int N, int PN3>
-__device__ __forceinline__ void zeta_pass(double* lr, int item, int epb, const double iw[N], const double* pia,
+__device__ __forceinline__ void zeta_pass(double* lr, int epb, const double (&iw)[2][N], const double* pia,
                                           const double* pib) {
     constexpr int N2 = N * N, SLOT = 5 * PN3, EBLK = 3 * SLOT;
-    if (item >= epb * N2) return;
-    const int eli = item / N2, l = item - eli * N2;   // zeta line: base l, stride N^2
 #pragma unroll
-    for (int st = 0; st < 5; ++st) {
+    for (int j = 0; j < 2; ++j) {
+        const int it = threadIdx.x + j * blockDim.x;
+        if (it >= epb * 5 * N2) break;
+        const int l = it % N2, sl = it / N2;   // zeta line (base l, stride N^2); element * 5 + state
+        const int eli = sl / 5, st = sl - eli * 5;
         double* x = lr + eli * EBLK + st * PN3;
         double v[N];
         double t = 0.0;
@@ -98,7 +102,7 @@ __device__ __forceinline__ void zeta_pass(double* lr, int item, int epb, const d
             t += pia[a] * v[a];
         }
 #pragma unroll
-        for (int a = 0; a < N; ++a) v[a] = (v[a] - pib[a] * t) * iw[a];
+        for (int a = 0; a < N; ++a) v[a] = (v[a] - pib[a] * t) * iw[j][a];
         t = 0.0;
 #pragma unroll
         for (int a = 0; a < N; ++a) t += pib[a] * v[a];
@@ -164,10 +168,37 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
             for (int a = 0; a < N; ++a) cl[m][a] = Cg[(int64_t)m * SE + a * N2];
     }
 
+    // ---- 1. stage the workgroup's elements: thread tid takes the nodes
+    //         tid + j * nth, j < KS (nth >= epb * 3 N^2, so KS = ceil(N / 3)
+    //         covers epb N^3). All state (and at p = 3 metric) loads are
+    //         issued first, then the face traces below, then the primitives
+    //         are formed, so that the staging's own data is not queued behind
+    //         the traces.
+    constexpr int KS = (N + 2) / 3;
+    constexpr int NCS = MLDS ? 9 : 1;
+    double su[KS][5], sc[KS][NCS];
+#pragma unroll
+    for (int j = 0; j < KS; ++j) {
+        const int idx = tid + j * nth;
+        const int eli = idx / N3, node = idx - eli * N3;
+        const int64_t ee = e0 + eli;
+        if (idx < epb * N3 && ee < E) {
+            const double* U = A.Uin + ee * N3 + node;
+#pragma unroll
+            for (int s = 0; s < 5; ++s) su[j][s] = U[s * SE];
+            if (MLDS) {
+                const double* Cg = A.geo.Cline + ee * N3 + node;   // same offset in line-major order
+#pragma unroll
+                for (int k = 0; k < NCS; ++k) sc[j][k] = Cg[k * SE];
+            }
+        }
+    }
+
     // line geometry, and the traces of the two face neighbours across the
     // line's ends (periodic box): conserved state and metric column at the
     // neighbour's end node (and, with local Lax-Friedrichs, the own conserved
-    // state). Requested before the staging so that their latency overlaps it.
+    // state). Requested before the primitives are formed, so that their latency
+    // overlaps the staging.
     // A neighbour inside the workgroup's own element range (the workgroup's
     // elements are consecutive, so most xi-neighbours are) has its primitives
     // staged in LDS: its state is not loaded (fin = its local index). The
@@ -199,13 +230,13 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
         }
     }
 
-    // ---- 1. primitives (and at p = 3 the metric columns) of the workgroup's elements -> LDS
-    for (int idx = tid; idx < epb * N3; idx += nth) {
+    // primitives (and at p = 3 the metric columns) -> LDS
+#pragma unroll
+    for (int j = 0; j < KS; ++j) {
+        const int idx = tid + j * nth;
         const int eli = idx / N3, node = idx - eli * N3;
-        const int64_t ee = e0 + eli;
-        if (ee < E) {
-            const double* U = A.Uin + ee * N3 + node;
-            PrimR q = primitives_ref(U[0], U[SE], U[2 * SE], U[3 * SE], U[4 * SE], gm1, pref);
+        if (idx < epb * N3 && e0 + eli < E) {
+            const PrimR q = primitives_ref(su[j][0], su[j][1], su[j][2], su[j][3], su[j][4], gm1, pref);
             double* L = lds + eli * LDSE + pad_node<N>(node);
             L[0] = q.rho;
             L[PN3] = q.u;
@@ -214,10 +245,9 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
             L[4 * PN3] = q.pd;
             L[5 * PN3] = q.beta;
             if (MLDS) {
-                const double* Cg = A.geo.Cline + ee * N3 + node;   // same offset in line-major order
                 double* Lc0 = lds + eli * LDSE + 6 * PN3 + node;
 #pragma unroll
-                for (int k = 0; k < 9; ++k) Lc0[k * N3] = Cg[k * SE];
+                for (int k = 0; k < NCS; ++k) Lc0[k * N3] = sc[j][k];
             }
         }
     }
@@ -276,12 +306,12 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
         }
     }
     // The node-parallel epilogue gives thread tid the nodes tid + j * nth,
-    // j < KP (nth >= epb * 3 N^2); with the weight-adjusted inverse the thread
-    // also scales the zeta-line `tid` (when tid < epb N^2). Request their
-    // global operands now, so that the latency overlaps the LDS passes.
+    // j < KP (nth >= epb * 3 N^2); with the weight-adjusted inverse it also
+    // scales the zeta-line items of zeta_pass. Request their global operands
+    // now, so that the latency overlaps the LDS passes.
     constexpr int KP = (N + 2) / 3;
     const int mode = A.mode;
-    double pf_iw[KP], pf_a[KP][5], pf_b[KP][5], zw[N];
+    double pf_iw[KP], pf_a[KP][5], pf_b[KP][5], zw[2][N];
     auto fetch_epilogue = [&]() {
 #pragma unroll
         for (int j = 0; j < KP; ++j) {
@@ -303,13 +333,15 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
             }
         }
 #pragma unroll
-        for (int a = 0; a < N; ++a) zw[a] = 0.0;
-        if (CWA && mode != MODE_RESIDUAL && tid < epb * N2) {
-            const int eli = tid / N2, zl = tid - eli * N2;
-            if (e0 + eli < E) {
+        for (int j = 0; j < 2; ++j) {
+            const int it = tid + j * nth;
+            const int zl = it % N2, eli = it / N2 / 5;
+#pragma unroll
+            for (int a = 0; a < N; ++a) zw[j][a] = 0.0;
+            if (CWA && mode != MODE_RESIDUAL && it < epb * 5 * N2 && e0 + eli < E) {
                 const double* iw = A.geo.invWJ + (e0 + eli) * N3 + zl;
 #pragma unroll
-                for (int a = 0; a < N; ++a) zw[a] = iw[a * N2];
+                for (int a = 0; a < N; ++a) zw[j][a] = iw[a * N2];
             }
         }
     };
@@ -373,7 +405,7 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
     if (CWA) {
         plane_pass<N, PN3, true>(lr, epb, A.ops.pia, A.ops.pib);   // sum of the slots, P^T along xi, eta
         __syncthreads();
-        zeta_pass<N, PN3>(lr, tid, epb, zw, A.ops.pia, A.ops.pib);   // P^T, 1/(W J), P along zeta
+        zeta_pass<N, PN3>(lr, epb, zw, A.ops.pia, A.ops.pib);   // P^T, 1/(W J), P along zeta
         __syncthreads();
         plane_pass<N, PN3, false>(lr, epb, A.ops.pib, A.ops.pia);   // P along xi, eta
         __syncthreads();
