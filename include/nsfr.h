@@ -74,7 +74,7 @@ typedef struct {
     int32_t source;       /* 0: none; 1: manufactured-solution source of Sec. 7.1        */
     int32_t tile;         /* elements per workgroup of the stage kernel, 3 (p+1)^2 threads
                              (one per line) each, within 512 threads and 64 KB of LDS
-                             (p = 2..5: at most 15, 6, 3, 2); 0 = tuned default. Must be
+                             (p = 2..5: at most 14, 6, 3, 2); 0 = tuned default. Must be
                              0 with quad = 1                                            */
     int32_t quad;         /* volume and surface quadrature (Sec. 3.3, Sec. 7 opening
                              paragraph): 0 = the LGL nodes themselves (collocated NSFR);

@@ -26,7 +26,10 @@ namespace nsfr {
 constexpr int STAGE_BLOCK_MAX = 512;
 
 // Accumulator layout after the line sweep: per element three slots (one per
-// line direction) of [5][PN3] (padded node index), EBLK = 3 SLOT doubles per
+// line direction) of [5][SPN] (padded node index; SPN = N^3 + N^2 + 1, one
+// more than the padded block, so that the five states of a slot start on
+// different LDS banks and the plane passes, whose lanes read the same node of
+// different (state, plane) blocks, do not conflict), EBLK = 3 SLOT doubles per
 // element.
 //
 // The weight-adjusted inverse Pi~ (W J)^-1 Pi~^T with Pi~ = P (x) P (x) P,
@@ -40,13 +43,13 @@ constexpr int STAGE_BLOCK_MAX = 512;
 // zeta-plane) of the workgroup: w <- w - vec (coef . w) on each xi-row, then
 // on each eta-column. With SUM the input is the sum of the three direction
 // slots (fixed order) and the result goes to slot 0.
-template <int N, int PN3, bool SUM>
+template <int N, int SPN, bool SUM>
 __device__ __forceinline__ void plane_pass(double* lr, int epb, const double* coef, const double* vec) {
-    constexpr int N2 = N * N, SLOT = 5 * PN3, EBLK = 3 * SLOT;
+    constexpr int N2 = N * N, SLOT = 5 * SPN, EBLK = 3 * SLOT;
     for (int it = threadIdx.x; it < epb * 5 * N; it += blockDim.x) {
         const int k = it % N, sl = it / N;   // zeta plane; element * 5 + state
         const int eli = sl / 5, st = sl - eli * 5;
-        double* x = lr + eli * EBLK + st * PN3;
+        double* x = lr + eli * EBLK + st * SPN;
         double w[N][N];   // [eta][xi]
 #pragma unroll
         for (int j = 0; j < N; ++j)
@@ -83,17 +86,17 @@ __device__ __forceinline__ void plane_pass(double* lr, int epb, const double* co
 // threads as item tid + j * nth, j < 2 (nth >= epb * 3 N^2 covers them in
 // two rounds); iw[j] holds 1/(W J) at item j's nodes, prefetched by the
 // caller.
-template <int N, int PN3>
+template <int N, int SPN>
 __device__ __forceinline__ void zeta_pass(double* lr, int epb, const double (&iw)[2][N], const double* pia,
                                           const double* pib) {
-    constexpr int N2 = N * N, SLOT = 5 * PN3, EBLK = 3 * SLOT;
+    constexpr int N2 = N * N, SLOT = 5 * SPN, EBLK = 3 * SLOT;
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
         const int it = threadIdx.x + j * blockDim.x;
         if (it >= epb * 5 * N2) break;
         const int l = it % N2, sl = it / N2;   // zeta line (base l, stride N^2); element * 5 + state
         const int eli = sl / 5, st = sl - eli * 5;
-        double* x = lr + eli * EBLK + st * PN3;
+        double* x = lr + eli * EBLK + st * SPN;
         double v[N];
         double t = 0.0;
 #pragma unroll
@@ -123,10 +126,10 @@ __host__ __device__ constexpr bool metric_in_lds(int p) { return p == 3; }
 
 // LDS per element (doubles): during the sweep the primitives [6][PN3]
 // (padded) and at p = 3 the metric columns [9][N3]; afterwards the three
-// direction slots [3][5][PN3] of the accumulator.
+// direction slots [3][5][SPN] of the accumulator.
 __host__ __device__ constexpr int stage_lds_per_elem(int n) {
     const int sweep = 6 * (n * n * n + n * n) + (metric_in_lds(n - 1) ? 9 * n * n * n : 0);
-    const int acc = 15 * (n * n * n + n * n);
+    const int acc = 15 * (n * n * n + n * n + 1);
     return sweep > acc ? sweep : acc;
 }
 
@@ -138,7 +141,8 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
     constexpr int N = P + 1, N2 = N * N, N3 = N2 * N, LINES = 3 * N2;
     constexpr int PN3 = padded_block<N>();          // padded stride of a primitive component
     constexpr bool MLDS = metric_in_lds(P);
-    constexpr int SLOT = 5 * PN3, EBLK = 3 * SLOT;    // direction slots of the accumulator
+    constexpr int SPN = PN3 + 1;                      // state stride of an accumulator slot
+    constexpr int SLOT = 5 * SPN, EBLK = 3 * SLOT;    // direction slots of the accumulator
     constexpr int LDSE = stage_lds_per_elem(N);         // LDS doubles per element
     const int tid = threadIdx.x, nth = blockDim.x;
     const int epb = A.epb;
@@ -358,12 +362,12 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
 #pragma unroll
         for (int s = 0; s < 5; ++s)
 #pragma unroll
-            for (int a = 0; a < N; ++a) x[s * PN3 + pad_node<N>(base + a * stride)] = R[s][a] * wperp;
+            for (int a = 0; a < N; ++a) x[s * SPN + pad_node<N>(base + a * stride)] = R[s][a] * wperp;
     }
     __syncthreads();
     // residual of (element, state, node): the three directions summed in a fixed order
     auto rsum = [&](int eli, int s, int node) {
-        const double* x = lr + eli * EBLK + s * PN3 + pad_node<N>(node);
+        const double* x = lr + eli * EBLK + s * SPN + pad_node<N>(node);
         return (x[0] + x[SLOT]) + x[2 * SLOT];
     };
 
@@ -385,7 +389,7 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
                 double wj = 1.0 / A.geo.invWJ[ee * N3 + node];
                 double* x = lr + eli * EBLK + pad_node<N>(node);   // slot 0
 #pragma unroll
-                for (int s = 0; s < 5; ++s) x[s * PN3] -= wj * qs[s];
+                for (int s = 0; s < 5; ++s) x[s * SPN] -= wj * qs[s];
             }
         }
         __syncthreads();
@@ -403,11 +407,11 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
         return;
     }
     if (CWA) {
-        plane_pass<N, PN3, true>(lr, epb, A.ops.pia, A.ops.pib);   // sum of the slots, P^T along xi, eta
+        plane_pass<N, SPN, true>(lr, epb, A.ops.pia, A.ops.pib);   // sum of the slots, P^T along xi, eta
         __syncthreads();
-        zeta_pass<N, PN3>(lr, epb, zw, A.ops.pia, A.ops.pib);   // P^T, 1/(W J), P along zeta
+        zeta_pass<N, SPN>(lr, epb, zw, A.ops.pia, A.ops.pib);   // P^T, 1/(W J), P along zeta
         __syncthreads();
-        plane_pass<N, PN3, false>(lr, epb, A.ops.pib, A.ops.pia);   // P along xi, eta
+        plane_pass<N, SPN, false>(lr, epb, A.ops.pib, A.ops.pia);   // P along xi, eta
         __syncthreads();
     }
 #pragma unroll
@@ -419,7 +423,7 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
         const int64_t g = ee * N3 + node;
 #pragma unroll
         for (int s = 0; s < 5; ++s) {
-            const double k = CWA ? -lr[eli * EBLK + s * PN3 + pad_node<N>(node)] : -(rsum(eli, s, node) * pf_iw[j]);
+            const double k = CWA ? -lr[eli * EBLK + s * SPN + pad_node<N>(node)] : -(rsum(eli, s, node) * pf_iw[j]);
             const int64_t gi = s * SE + g;
             switch (mode) {
                 case MODE_RHS: A.out[gi] = k; break;
