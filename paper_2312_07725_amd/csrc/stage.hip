@@ -505,7 +505,7 @@ int default_epb(int p) {
         case 2: d = 2; break;
         case 3: d = 4; break;
         case 4: d = 3; break;
-        default: d = 1; break;
+        default: d = 2; break;
     }
     const int m = max_epb(p);
     return d < m ? d : m;

@@ -1,6 +1,6 @@
 """Autotuner for the stage-kernel tile (elements per workgroup) per degree.
 
-    python -m paper_2312_07725_amd.tune [--ne 16] [--reps 200] [--out PATH]
+    python -m paper_2312_07725_amd.tune [--ne 16,32] [--reps 200] [--out PATH]
     python -m paper_2312_07725_amd.tune --ensemble [--reps 50] [--out PATH]
 
 For every p in 2..5 it times the full right-hand side (nsfr_rhs: volume and
@@ -106,30 +106,53 @@ def time_rhs(g, U, out, reps):
     return statistics.median(times)
 
 
-def tune(ne=16, reps=200, ps=(2, 3, 4, 5), out=TILES_PATH, verbose=True):
+def tune(nes=(16, 32), reps=200, ps=(2, 3, 4, 5), out=TILES_PATH, verbose=True):
+    """Time nsfr_rhs of the warped TGV (c = c_HU) for every valid tile on each
+    mesh in nes; per degree keep the tile whose worst slowdown against the
+    fastest tile of each mesh is smallest. The ensemble section of an
+    existing table is kept."""
     from . import inputs
     from .nsfr import NSFR, NSFRError, c_hu
     table = {}
     for p in ps:
-        res = {}
-        X = None
-        for epb in range(1, 33):
-            try:
-                g = NSFR(p, ne, beta=0.2, c=c_hu(p), tile=epb)
-            except NSFRError:
-                continue
-            if X is None:
-                X = g.node_coords().cpu()
-                U = inputs.tgv_state(X).cuda().contiguous()
-            o = g.empty()
-            res[epb] = time_rhs(g, U, o, reps)
-            if verbose:
-                print(f"p={p} epb={epb}: {res[epb]:.2f} us", flush=True)
-            del g, o
-        best = min(res, key=res.get)
-        table[str(p)] = {"epb": best, "rhs_us": res[best], "all_us": {str(k): v for k, v in res.items()}}
-    doc = {"device": torch.cuda.get_device_name(0), "mesh": f"{ne}^3 warped TGV (beta=0.2), c=c_HU",
-           "metric": "median time of one nsfr_rhs (us)", "tiles": table}
+        per_ne = {}
+        for ne in nes:
+            res = {}
+            U = None
+            for epb in range(1, 33):
+                try:
+                    g = NSFR(p, ne, beta=0.2, c=c_hu(p), tile=epb)
+                except NSFRError:
+                    continue
+                if U is None:
+                    U = inputs.tgv_state(g.node_coords().cpu()).cuda().contiguous()
+                o = g.empty()
+                res[epb] = time_rhs(g, U, o, reps)
+                if verbose:
+                    print(f"p={p} ne={ne} epb={epb}: {res[epb]:.2f} us", flush=True)
+                del g, o
+            per_ne[ne] = res
+        common = set.intersection(*(set(r) for r in per_ne.values()))
+        worst = {t: max(per_ne[ne][t] / min(per_ne[ne].values()) for ne in nes) for t in common}
+        best = min(sorted(common), key=worst.get)
+        entry = {"epb": best, "worst_slowdown": worst[best]}
+        for ne in nes:
+            entry[f"rhs_us_{ne}"] = per_ne[ne][best]
+            entry[f"all_us_{ne}"] = {str(k): v for k, v in sorted(per_ne[ne].items())}
+        table[str(p)] = entry
+    try:
+        with open(out) as fh:
+            old = json.load(fh)
+    except (OSError, ValueError, TypeError):
+        old = {}
+    doc = {"device": torch.cuda.get_device_name(0),
+           "mesh": " and ".join(f"{ne}^3" for ne in nes) + " warped TGV (beta=0.2), c=c_HU",
+           "metric": "median time of one nsfr_rhs (us)",
+           "rule": "per degree the tile with the smallest worst slowdown against the fastest tile of each mesh",
+           "tiles": table}
+    for k in ("ensemble_tiles", "ensemble"):
+        if k in old:
+            doc[k] = old[k]
     if out:
         with open(out, "w") as fh:
             json.dump(doc, fh, indent=1)
@@ -138,7 +161,7 @@ def tune(ne=16, reps=200, ps=(2, 3, 4, 5), out=TILES_PATH, verbose=True):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--ne", type=int, default=16)
+    ap.add_argument("--ne", default="16,32", help="comma-separated mesh sizes")
     ap.add_argument("--reps", type=int, default=200)
     ap.add_argument("--out", default=TILES_PATH)
     ap.add_argument("--ensemble", action="store_true", help="tune the ensemble kernels' tiles on the ensemble")
@@ -147,7 +170,7 @@ def main():
         doc = tune_ensemble(a.reps, out=a.out)
         json.dump({k: v["epb"] for k, v in doc["ensemble_tiles"].items()}, sys.stdout)
     else:
-        doc = tune(a.ne, a.reps, out=a.out)
+        doc = tune(tuple(int(v) for v in str(a.ne).split(",")), a.reps, out=a.out)
         json.dump({k: v["epb"] for k, v in doc["tiles"].items()}, sys.stdout)
     print()
 
