@@ -106,6 +106,18 @@ def time_rhs(g, U, out, reps):
     return statistics.median(times)
 
 
+def select_tile(per_mesh):
+    """per_mesh: {mesh: {tile: time}}. Returns (tile, worst slowdown): among
+    the tiles timed on every mesh, the one whose largest ratio to the fastest
+    time of a mesh is smallest (ties to the smaller tile)."""
+    common = set.intersection(*(set(r) for r in per_mesh.values()))
+    if not common:
+        raise ValueError("no tile was timed on every mesh")
+    worst = {t: max(r[t] / min(r.values()) for r in per_mesh.values()) for t in common}
+    best = min(sorted(common), key=worst.get)
+    return best, worst[best]
+
+
 def tune(nes=(16, 32), reps=200, ps=(2, 3, 4, 5), out=TILES_PATH, verbose=True):
     """Time nsfr_rhs of the warped TGV (c = c_HU) for every valid tile on each
     mesh in nes; per degree keep the tile whose worst slowdown against the
@@ -132,10 +144,8 @@ def tune(nes=(16, 32), reps=200, ps=(2, 3, 4, 5), out=TILES_PATH, verbose=True):
                     print(f"p={p} ne={ne} epb={epb}: {res[epb]:.2f} us", flush=True)
                 del g, o
             per_ne[ne] = res
-        common = set.intersection(*(set(r) for r in per_ne.values()))
-        worst = {t: max(per_ne[ne][t] / min(per_ne[ne].values()) for ne in nes) for t in common}
-        best = min(sorted(common), key=worst.get)
-        entry = {"epb": best, "worst_slowdown": worst[best]}
+        best, worst = select_tile(per_ne)
+        entry = {"epb": best, "worst_slowdown": worst}
         for ne in nes:
             entry[f"rhs_us_{ne}"] = per_ne[ne][best]
             entry[f"all_us_{ne}"] = {str(k): v for k, v in sorted(per_ne[ne].items())}
