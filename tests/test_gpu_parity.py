@@ -12,8 +12,9 @@ density residual is pure truncation error.
 Cases span p = 2..5, ragged element counts (so the last workgroup is partial),
 the single-element periodic mesh, both two-point flux variants, c = 0 and
 c = c_HU (weight-adjusted inverse with the rank-one FR projection), the
-dissipative surface flux with the manufactured source, and the full 16^3 TGV
-meshes (sampled elements) in the launch configuration the benchmark times.
+dissipative surface flux with the manufactured source, and the full 16^3 (p =
+3, 4, 5) and 32^3 (p = 3) TGV meshes (sampled elements) in the launch
+configuration the benchmark times.
 """
 import numpy as np
 import pytest
@@ -130,6 +131,24 @@ def test_full_size_tgv_16(p, lib):
     assert_ext(got, xs.rhs(Un), [x64.rhs(Un), o.rhs(U)[:, Et]], f"16^3 p={p} rhs")
     R = g.residual(cuda(U)).cpu()[:, Et]
     assert_ext(R, xs.residual(Un), [x64.residual(Un), o.residual(U)[:, Et]], f"16^3 p={p} residual")
+
+
+def test_full_size_tgv_32(lib):
+    """32^3 warped TGV, p = 3, c = c_HU (the benchmark's 32^3 configuration,
+    eight workgroup rounds at the default tile): 64 sampled elements against
+    the extended evaluation."""
+    p = 3
+    c = oracle.operators.c_hu(p)
+    g, o = make_pair(p, 32, beta=0.2, c=c)
+    U = state(o, "tgv")
+    E = 32 ** 3
+    els = np.unique(np.concatenate([[0, E - 1], np.random.default_rng(32).choice(E, 62, replace=False)]))
+    xs = make_ext(p, 32, beta=0.2, c=c, elements=els)
+    x64 = make_ext(p, 32, beta=0.2, c=c, elements=els, dt=np.float64)
+    Un = U.numpy()
+    Et = torch.as_tensor(els)
+    got = g.rhs(cuda(U)).cpu()[:, Et]
+    assert_ext(got, xs.rhs(Un), [x64.rhs(Un), o.rhs(U)[:, Et]], f"32^3 p={p} rhs")
 
 
 def test_smoke_case_plain_bar(lib):
