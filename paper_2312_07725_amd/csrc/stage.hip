@@ -11,7 +11,8 @@
 //
 // Work decomposition: a workgroup owns `epb` elements. Every element has
 // 3 (p+1)^2 lines (p+1)^2 per direction; one thread owns one line. Its line's
-// metric column and residual live in registers (primitives in LDS), all
+// residual lives in registers, the primitives (and at p = 3 the metric
+// columns) in LDS, all
 // (p+1) p / 2 node pairs are evaluated once each (pair symmetry), and the two
 // endpoint face fluxes of the line are computed by the same thread, so every
 // face node's surface term belongs to exactly one thread (no atomics; the
@@ -121,7 +122,7 @@ __device__ __forceinline__ void zeta_pass(double* lr, int epb, const double (&iw
 // 9 N3 doubles per element), elsewhere from registers loaded straight from
 // the line-major array. Under the 3-waves-per-SIMD register cap of p = 3 the
 // LDS copy can be re-read instead of spilled; at p = 4, 5 (no cap) holding
-// the column in registers is slightly faster and saves the LDS.
+// the column in registers measured slightly faster.
 __host__ __device__ constexpr bool metric_in_lds(int p) { return p == 3; }
 
 // LDS per element (doubles): during the sweep the primitives [6][PN3]
@@ -449,9 +450,10 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
 // threads per element of the stage kernel: one per line
 __host__ __device__ constexpr int stage_threads_per_elem(int n) { return 3 * n * n; }
 
-// Minimum waves per SIMD the register allocation must allow: at p = 3 a cap
-// of 168 VGPRs (3 waves; a few doubles spill) is faster than the 186-VGPR
-// allocation (2 waves); at p = 4, 5 the same cap spills heavily and is slower.
+// Minimum waves per SIMD the register allocation must allow: at p = 3 the
+// cap of 168 VGPRs (3 waves) holds the kernel without spill and is faster
+// than the uncapped allocation (2 waves); at p = 4, 5 the same cap spills
+// (192 B per lane at p = 4) and is about 1.5x slower.
 __host__ __device__ constexpr int stage_min_waves(int p) { return p == 3 ? 3 : 1; }
 
 template <int P, bool CWA, int VARIANT, int DISS>
