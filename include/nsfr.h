@@ -93,6 +93,17 @@ typedef struct {
                              differentiated in the flux basis, N . f* - n . phi_f f^r on
                              the faces, the same weight-adjusted inverse. Needs quad = 1
                              and surface_diss = 0; flux is ignored                       */
+    int32_t mass;         /* inverse of the FR-modified mass M_m + K_m (Eq. Km): 0 = the
+                             weight-adjusted approximation of Sec. 4 (Eq. weight-adj ESFR
+                             mass; the fast path); 1 = the exact inverse, for checking
+                             the approximation: the dense (p+1)^3 x (p+1)^3 matrix of
+                             every element is assembled and Cholesky-factorised at
+                             nsfr_create ((p+1)^6 doubles per element of device memory;
+                             NSFR_ENOMEM if that does not fit, NSFR_EUNPHYSICAL if a
+                             matrix is not positive definite) and nsfr_rhs applies it by
+                             two triangular solves. Needs quad = 0; nsfr_rk4_step,
+                             nsfr_rk4_step_static, nsfr_rk4_run, nsfr_rhs_vjp,
+                             nsfr_rk4_step_vjp and ensembles return NSFR_ENOTSUP       */
 } nsfr_config;
 
 typedef struct nsfr_ctx nsfr_ctx;

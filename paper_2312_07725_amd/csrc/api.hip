@@ -45,6 +45,8 @@ struct nsfr_ctx {
     double* Xq = nullptr;      // [3][E][q^3]
     double* vhat = nullptr;    // [5][E][n^3] projected entropy variables of the last stage's input
     double* ft = nullptr;      // [6][5][E][q^2] their face values
+    // exact mass inverse (cfg.mass = 1): Cholesky factor of M_m + K_m per element
+    double* Lmass = nullptr;   // [E][n^3][n^3], lower triangle
     // graph cache for nsfr_rk4_run
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
@@ -90,6 +92,8 @@ static nsfr_status validate(const nsfr_config* c) {
     if (c->quad == 0 && c->overint != 0) return bad("overintegration needs the Gauss-Legendre rule (quad = 1)");
     if (c->quad == 1 && c->scheme == 0 && c->tile > 1)
         return bad("the NSFR Gauss-Legendre kernel runs one element per workgroup (tile must be 0 or 1)");
+    if (c->mass < 0 || c->mass > 1) return bad("mass must be 0 (weight-adjusted) or 1 (exact inverse)");
+    if (c->mass == 1 && c->quad != 0) return bad("the exact mass inverse is built for the collocated scheme (quad = 0)");
     return NSFR_OK;
 }
 
@@ -107,7 +111,7 @@ static void free_ctx(nsfr_ctx* c) {
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
     double* bufs[] = {c->X, c->Cline, c->invWJ, c->J, c->wsR, c->wsR2, c->red,
-                      c->Cq, c->Cf, c->invWJq, c->Xq, c->vhat, c->ft};
+                      c->Cq, c->Cf, c->invWJq, c->Xq, c->vhat, c->ft, c->Lmass};
     for (double* b : bufs)
         if (b) (void)hipFree(b);
     if (c->cnt) (void)hipFree(c->cnt);
@@ -201,6 +205,31 @@ const char* nsfr_last_error(void) { return g_last_error.c_str(); }
 
 // Gauss-Legendre operators, metric terms at the quadrature points and the
 // projection buffers (the context's LGL geometry is already built).
+// Dense M_m + K_m of every element and its Cholesky factor (cfg.mass = 1).
+static nsfr_status exact_mass_setup(nsfr_ctx* c) {
+    const size_t nd = exact_mass_doubles(c->p, c->E);
+    if (hipMalloc((void**)&c->Lmass, nd * sizeof(double)) != hipSuccess) {
+        set_error("hipMalloc failed for the exact mass factors (" + std::to_string(nd * sizeof(double)) + " bytes)");
+        return NSFR_ENOMEM;
+    }
+    HIP_TRY(hipMemsetAsync(c->cnt, 0, sizeof(int32_t), c->stream));
+    HIP_TRY(launch_exact_mass_factor(c->p, c->E, c->invWJ, c->hops.d, c->cfg.c_fr, c->Lmass, c->cnt, c->stream));
+    int32_t fail = 0;
+    HIP_TRY(hipMemcpyAsync(&fail, c->cnt, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (fail) {
+        set_error("the FR-modified mass of an element is not positive definite");
+        return NSFR_EUNPHYSICAL;
+    }
+    return NSFR_OK;
+}
+
+static nsfr_status exact_mass_unsupported(const nsfr_ctx* c, const char* what) {
+    if (!c->cfg.mass) return NSFR_OK;
+    set_error(std::string(what) + ": the exact mass inverse (mass = 1) is offered by nsfr_rhs only");
+    return NSFR_ENOTSUP;
+}
+
 static nsfr_status gl_setup(nsfr_ctx* c) {
     const int q = c->n + c->cfg.overint;
     c->q = q;
@@ -334,6 +363,13 @@ nsfr_status nsfr_create(const nsfr_config* cfg, void* hip_stream, nsfr_ctx** out
             free_ctx(c);
             return NSFR_EUNPHYSICAL;
         }
+    if (cfg->mass) {
+        st = exact_mass_setup(c);
+        if (st != NSFR_OK) {
+            free_ctx(c);
+            return st;
+        }
+    }
     if (cfg->quad) {
         st = gl_setup(c);
         if (st != NSFR_OK) {
@@ -402,6 +438,13 @@ nsfr_status nsfr_rhs(nsfr_ctx* c, const double* U, double* dUdt, double t) {
     a.Uin = U;
     a.out = dUdt;
     a.t = t;
+    if (c->cfg.mass) {   // residual, then -(M_m + K_m)^-1 R
+        a.out = c->wsR;
+        a.mode = MODE_RESIDUAL;
+        if ((st = stage(c, a))) return st;
+        HIP_TRY(launch_exact_mass_solve(c->p, c->E, c->Lmass, c->wsR, dUdt, c->stream));
+        return NSFR_OK;
+    }
     a.mode = MODE_RHS;
     return stage(c, a);
 }
@@ -426,6 +469,7 @@ static nsfr_status rk4_enqueue(nsfr_ctx* c, double* U, const double* dt, double 
 
 nsfr_status nsfr_rk4_step(nsfr_ctx* c, double* U, const double* dt, double t, double* work) {
     if (!c || !aligned(U) || !aligned(dt) || !aligned(work)) return bad("null or misaligned argument");
+    if (exact_mass_unsupported(c, "nsfr_rk4_step")) return NSFR_ENOTSUP;
     nsfr_status st = use_device(c);
     if (st) return st;
     return rk4_enqueue(c, U, dt, t, nullptr, work);
@@ -433,6 +477,7 @@ nsfr_status nsfr_rk4_step(nsfr_ctx* c, double* U, const double* dt, double t, do
 
 nsfr_status nsfr_rk4_step_static(nsfr_ctx* c, double* U, const double* dt, double t) {
     if (!c || !aligned(U) || !aligned(dt)) return bad("null or misaligned argument");
+    if (exact_mass_unsupported(c, "nsfr_rk4_step_static")) return NSFR_ENOTSUP;
     const int64_t nodes = c->E * (int64_t)c->n3;
     if (nodes > NSFR_STATIC_MAX_NODES)
         return bad("nsfr_rk4_step_static: the mesh has " + std::to_string(nodes) +
@@ -448,6 +493,7 @@ nsfr_status nsfr_rk4_run(nsfr_ctx* c, double* U, const double* dt, double* tdev,
     if (!c || !aligned(U) || !aligned(dt) || (tdev && !aligned(tdev)) || !aligned(work) || nsteps < 0)
         return bad("null, misaligned or negative argument");
     if (!tdev && c->cfg.source) return bad("t_dev is required when the source term is enabled");
+    if (exact_mass_unsupported(c, "nsfr_rk4_run")) return NSFR_ENOTSUP;
     nsfr_status st = use_device(c);
     if (st) return st;
     if (nsteps == 0) return NSFR_OK;
@@ -547,6 +593,7 @@ nsfr_status nsfr_rhs_vjp(nsfr_ctx* c, const double* U, const double* lam, double
     (void)t;   // the source term does not depend on U
     if (!c || !aligned(U) || !aligned(lam) || !aligned(g) || g == U || g == lam)
         return bad("null, misaligned or aliased argument");
+    if (exact_mass_unsupported(c, "nsfr_rhs_vjp")) return NSFR_ENOTSUP;
     if (c->cfg.surface_diss || c->cfg.quad) {
         set_error("rhs_vjp supports the collocated scheme with the entropy-conserving surface flux only "
                   "(surface_diss = 0, quad = 0)");
@@ -568,6 +615,7 @@ nsfr_status nsfr_rk4_step_vjp(nsfr_ctx* c, const double* U, const double* dt, do
                               double* lam, double* work) {
     if (!c || !aligned(U) || !aligned(dt) || !aligned(lam_next) || !aligned(lam) || !aligned(work) || lam == U)
         return bad("null, misaligned or aliased argument");
+    if (exact_mass_unsupported(c, "nsfr_rk4_step_vjp")) return NSFR_ENOTSUP;
     if (c->cfg.surface_diss || c->cfg.quad) {
         set_error("rk4_step_vjp supports the collocated scheme with the entropy-conserving surface flux only "
                   "(surface_diss = 0, quad = 0)");

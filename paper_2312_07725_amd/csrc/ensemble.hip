@@ -189,9 +189,9 @@ nsfr_status nsfr_ens_create(const nsfr_config* cfgs, int32_t n, void* stream, ns
     s->offs.push_back(0);
     for (int f = 0; f < n; ++f) {
         nsfr_config c = cfgs[f];
-        if (c.source || c.surface_diss || c.quad) {
-            set_error("ensemble flows take the collocated LGL scheme with the entropy-conserving surface flux "
-                      "and no source term");
+        if (c.source || c.surface_diss || c.quad || c.mass) {
+            set_error("ensemble flows take the collocated LGL scheme with the entropy-conserving surface flux, "
+                      "no source term and the weight-adjusted mass inverse");
             ens_free(s);
             return NSFR_ENOTSUP;
         }

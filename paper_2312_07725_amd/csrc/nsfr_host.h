@@ -98,6 +98,11 @@ struct FlowDesc;   // ensemble (ensemble.hip)
 hipError_t launch_geometry(int p, const Ops& ops, int nx, int ny, int nz, double lo, double hi, double beta,
                            double l, double* X, double* Cline, double* invWJ, double* J, hipStream_t s);
 hipError_t launch_stage(int p, bool cwa, int variant, const StageArgs& a, hipStream_t s);
+// exact inverse of the FR-modified mass (exact_mass.hip): L [E][n^3][n^3]
+size_t exact_mass_doubles(int p, int64_t E);
+hipError_t launch_exact_mass_factor(int p, int64_t E, const double* invWJ, const double* d, double c, double* L,
+                                    int* fail, hipStream_t s);
+hipError_t launch_exact_mass_solve(int p, int64_t E, const double* L, const double* R, double* out, hipStream_t s);
 int default_epb(int p);
 size_t stage_lds_bytes(int p, int epb);
 int max_epb(int p);

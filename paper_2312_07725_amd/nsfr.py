@@ -26,7 +26,7 @@ class Config(ctypes.Structure):
         ("lo", c_double), ("hi", c_double), ("warp_beta", c_double), ("warp_l", c_double),
         ("gamma", c_double), ("c_fr", c_double),
         ("flux", c_int32), ("surface_diss", c_int32), ("source", c_int32), ("tile", c_int32),
-        ("quad", c_int32), ("overint", c_int32), ("scheme", c_int32),
+        ("quad", c_int32), ("overint", c_int32), ("scheme", c_int32), ("mass", c_int32),
     ]
 
 
@@ -106,7 +106,7 @@ def c_hu(p):
 
 
 def make_config(p, ne, lo=0.0, hi=2 * math.pi, beta=0.0, l=0.0, gamma=1.4, c=0.0, flux=0, diss=0, source=0, tile=0,
-                quad=0, overint=0, scheme=0):
+                quad=0, overint=0, scheme=0, mass=0):
     if isinstance(ne, int):
         ne = (ne, ne, ne)
     cfg = Config()
@@ -116,7 +116,7 @@ def make_config(p, ne, lo=0.0, hi=2 * math.pi, beta=0.0, l=0.0, gamma=1.4, c=0.0
     cfg.warp_beta, cfg.warp_l = float(beta), float(l or 0.0)
     cfg.gamma, cfg.c_fr = float(gamma), float(c)
     cfg.flux, cfg.surface_diss, cfg.source, cfg.tile = int(flux), int(diss), int(source), int(tile)
-    cfg.quad, cfg.overint, cfg.scheme = int(quad), int(overint), int(scheme)
+    cfg.quad, cfg.overint, cfg.scheme, cfg.mass = int(quad), int(overint), int(scheme), int(mass)
     return cfg
 
 
@@ -126,10 +126,11 @@ class NSFR:
     quad = "lgl" (collocated, the default) or "gl" (Gauss-Legendre volume and
     surface rule with p + 1 + overint points per direction); scheme = "nsfr"
     (the default) or "dg" (conservative strong DG with Roe's flux, on the GL
-    rule)."""
+    rule); mass = "wa" (the weight-adjusted inverse, the default) or "exact"
+    (the exact inverse of the FR-modified mass, for checking; rhs only)."""
 
     def __init__(self, p, ne, lo=0.0, hi=2 * math.pi, beta=0.0, l=0.0, gamma=1.4, c=0.0, flux=0, diss=0,
-                 source=0, tile=0, quad="lgl", overint=0, scheme="nsfr"):
+                 source=0, tile=0, quad="lgl", overint=0, scheme="nsfr", mass="wa"):
         if not torch.cuda.is_available():
             raise RuntimeError("libnsfr needs a HIP GPU; none is visible")
         if quad not in ("lgl", "gl"):
@@ -137,12 +138,14 @@ class NSFR:
         q = 1 if quad == "gl" else 0
         if scheme not in ("nsfr", "dg"):
             raise ValueError(f"scheme must be 'nsfr' or 'dg', got {scheme!r}")
+        if mass not in ("wa", "exact"):
+            raise ValueError(f"mass must be 'wa' or 'exact', got {mass!r}")
         if not tile and not q:
             from .tune import load_tiles
             tile = load_tiles().get(int(p), 0)
         self.quad, self.overint, self.scheme = quad, int(overint), scheme
         self.cfg = make_config(p, ne, lo, hi, beta, l, gamma, c, flux, diss, source, tile, q, overint,
-                               1 if scheme == "dg" else 0)
+                               1 if scheme == "dg" else 0, 1 if mass == "exact" else 0)
         self.p, self.n = int(p), int(p) + 1
         self.gamma = float(gamma)
         self._ctx = c_void_p()

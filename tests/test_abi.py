@@ -67,17 +67,18 @@ def test_null_arguments(L):
 
 
 def test_config_layout_matches_header():
-    # int32 p, int32 ne[3], 6 doubles, 7 int32 = 92 bytes, padded to 96 (doubles 8-aligned)
+    # int32 p, int32 ne[3], 6 doubles, 8 int32 = 96 bytes
     assert ctypes.sizeof(nsfr.Config) == 96
     assert nsfr.Config.lo.offset == 16
     assert nsfr.Config.flux.offset == 64
     assert nsfr.Config.quad.offset == 80 and nsfr.Config.overint.offset == 84
-    assert nsfr.Config.scheme.offset == 88
+    assert nsfr.Config.scheme.offset == 88 and nsfr.Config.mass.offset == 92
 
 
 @pytest.mark.parametrize("kw", [dict(quad=1, tile=2), dict(scheme=2, quad=1), dict(scheme=1, quad=0),
                                 dict(scheme=1, quad=1, diss=1), dict(scheme=1, quad=1, overint=5),
-                                dict(scheme=0, quad=1, overint=4)])
+                                dict(scheme=0, quad=1, overint=4), dict(mass=2), dict(mass=-1),
+                                dict(mass=1, quad=1), dict(mass=1, quad=1, scheme=1)])
 def test_create_rejects_invalid_quadrature_or_scheme(L, kw):
     cfg = nsfr.make_config(3, 2, **kw)
     ctx = ctypes.c_void_p()
