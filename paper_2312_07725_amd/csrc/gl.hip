@@ -45,27 +45,30 @@ constexpr int DG_BLOCK = 512;   // DG stage (3 q^2 <= 432 line threads at q = 12
 // OUT x IN row-major, or its transpose stored IN x OUT when TR. One thread
 // per (block, line): the line's IN inputs are read once into registers and
 // its OUT outputs written once, so the index arithmetic is paid per line.
-template <int S0, int S1, int S2, int AX, int OUT, bool TR>
+template <int S0, int S1, int S2, int AX, int OUT, bool TR, int SP = S0, int DP = (AX == 0 ? OUT : S0)>
 __device__ __forceinline__ void lds_pass(const double* __restrict__ src, double* __restrict__ dst,
                                          const double* __restrict__ M, int ns) {
+    // SP, DP: pitch of an x-row in src and dst (>= the row length; a pitch
+    // that is odd spreads the lanes of the x- and y-passes over the LDS banks)
     constexpr int IN = AX == 0 ? S0 : (AX == 1 ? S1 : S2);
-    constexpr int D0 = AX == 0 ? OUT : S0;
-    constexpr int SRC = S0 * S1 * S2, NL = SRC / IN, DST = NL * OUT;
-    constexpr int SST = AX == 0 ? 1 : (AX == 1 ? S0 : S0 * S1);   // stride along the axis in src
-    constexpr int DSS = AX == 0 ? 1 : (AX == 1 ? D0 : S0 * S1);   // and in dst
+    constexpr int D1 = AX == 1 ? OUT : S1, D2 = AX == 2 ? OUT : S2;
+    constexpr int SRC = SP * S1 * S2, NL = S0 * S1 * S2 / IN, DST = DP * D1 * D2;
+    constexpr int SST = AX == 0 ? 1 : (AX == 1 ? SP : SP * S1);   // stride along the axis in src
+    constexpr int DSS = AX == 0 ? 1 : (AX == 1 ? DP : DP * D1);   // and in dst
     for (int it = threadIdx.x; it < ns * NL; it += blockDim.x) {
         const int b = it / NL, ln = it - b * NL;
         int sb, db;
         if (AX == 0) {          // ln = i1 + S1 i2
-            sb = ln * S0;
-            db = ln * OUT;
+            sb = ln * SP;
+            db = ln * DP;
         } else if (AX == 1) {   // ln = i0 + S0 i2
             const int i0 = ln % S0, i2 = ln / S0;
-            sb = i0 + S0 * S1 * i2;
-            db = i0 + S0 * OUT * i2;
+            sb = i0 + SP * S1 * i2;
+            db = i0 + DP * OUT * i2;
         } else {                // ln = i0 + S0 i1
-            sb = ln;
-            db = ln;
+            const int i0 = ln % S0, i1 = ln / S0;
+            sb = i0 + SP * i1;
+            db = i0 + DP * i1;
         }
         const double* x = src + b * SRC + sb;
         double v[IN];
@@ -82,20 +85,24 @@ __device__ __forceinline__ void lds_pass(const double* __restrict__ src, double*
     }
 }
 
+// An odd x-row pitch for a row of n values (n itself when odd).
+__host__ __device__ constexpr int odd_pitch(int n) { return n | 1; }
+
 // Face slabs of a coefficient array X [nb][5][n^3] (nb element blocks): copy
 // the six end slabs into SL [nb][6][5][n^2] (tangential indices in increasing
 // direction order, first fastest).
-template <int N>
+template <int N, int XP = N, int SLP = N>
 __device__ __forceinline__ void gather_slabs(const double* __restrict__ X, double* __restrict__ SL, int nb) {
-    constexpr int N2 = N * N, N3 = N2 * N;
+    // XP: x-row pitch of X's blocks; SLP: pitch of a slab's first tangential row
+    constexpr int N2 = N * N;
     for (int it = threadIdx.x; it < nb * 30 * N2; it += blockDim.x) {
         const int el = it / (30 * N2), r = it - el * 30 * N2;
         const int f = r / (5 * N2), r2 = r - f * 5 * N2;
         const int s = r2 / N2, t = r2 - s * N2;
         const int d = f / 2, end = (f % 2) ? N - 1 : 0;
         const int u1 = t % N, u2 = t / N;
-        const int nd = d == 0 ? end + N * u1 + N2 * u2 : (d == 1 ? u1 + N * end + N2 * u2 : u1 + N * u2 + N2 * end);
-        SL[it] = X[(el * 5 + s) * N3 + nd];
+        const int a = d == 0 ? end : u1, b = d == 0 ? u1 : (d == 1 ? end : u2), c = d == 2 ? end : u2;
+        SL[(el * 30 + f * 5 + s) * (SLP * N) + u1 + SLP * u2] = X[(el * 5 + s) * (XP * N2) + a + XP * (b + N * c)];
     }
 }
 
@@ -242,15 +249,19 @@ __global__ __launch_bounds__(GL_BLOCK) void gl_project_kernel(const GLOps* __res
                                                               const double* __restrict__ U, double gamma,
                                                               double* vhat, double* ft) {
     constexpr int N2 = N * N, N3 = N2 * N, Q2 = Q * Q, Q3 = Q2 * Q;
+    // x-row pitches of the LDS arrays (odd for the NSFR projection, so that the
+    // lanes of the x- and y-passes fall on different LDS banks)
+    constexpr int XN = DG ? N : odd_pitch(N), XQ = DG ? Q : odd_pitch(Q);
+    constexpr int BN = XN * N2, BQ = XQ * Q2;   // block sizes of an n^3 and a q^3 array
     extern __shared__ double lds[];
-    constexpr int AS = DG ? 5 * N3 : 5 * Q3, BS = DG ? 0 : 5 * Q3;
+    constexpr int AS = DG ? 5 * N3 : 5 * BQ, BS = DG ? 0 : 5 * BQ;
     double* mchi = lds;              // Q x N
     double* mpi = mchi + Q * N;      // N x Q
     double* A = mpi + N * Q;         // AS
     double* B = A + AS;              // BS
-    double* SL = B + BS;             // [6][5][N^2] end slabs
-    double* T = SL + 30 * N2;        // [6][5][Q N]
-    double* SF = T + 30 * Q * N;     // [6][5][Q^2]
+    double* SL = B + BS;             // [6][5][N^2] end slabs (row pitch XN)
+    double* T = SL + 30 * XN * N;    // [6][5][Q N] (row pitch XQ)
+    double* SF = T + 30 * XQ * N;    // [6][5][Q^2] (row pitch XQ)
     const int tid = threadIdx.x;
     const int64_t e = blockIdx.x;
     const int64_t SE = E * N3;
@@ -261,47 +272,48 @@ __global__ __launch_bounds__(GL_BLOCK) void gl_project_kernel(const GLOps* __res
     }
     for (int i = tid; i < 5 * N3; i += blockDim.x) {
         const int s = i / N3, nd = i - s * N3;
-        A[i] = U[s * SE + e * N3 + nd];
+        A[s * BN + nd % N + XN * (nd / N)] = U[s * SE + e * N3 + nd];
     }
     __syncthreads();
     if constexpr (!DG) {
-        lds_pass<N, N, N, 0, Q, false>(A, B, mchi, 5);
+        lds_pass<N, N, N, 0, Q, false, XN, XQ>(A, B, mchi, 5);
         __syncthreads();
-        lds_pass<Q, N, N, 1, Q, false>(B, A, mchi, 5);
+        lds_pass<Q, N, N, 1, Q, false, XQ, XQ>(B, A, mchi, 5);
         __syncthreads();
-        lds_pass<Q, Q, N, 2, Q, false>(A, B, mchi, 5);
+        lds_pass<Q, Q, N, 2, Q, false, XQ, XQ>(A, B, mchi, 5);
         __syncthreads();
         for (int t = tid; t < Q3; t += blockDim.x) {
+            const int pt = t % Q + XQ * (t / Q);
             double u[5], v[5];
 #pragma unroll
-            for (int s = 0; s < 5; ++s) u[s] = B[s * Q3 + t];
+            for (int s = 0; s < 5; ++s) u[s] = B[s * BQ + pt];
             entropy_vars(u, gm1, gamma, v);
 #pragma unroll
-            for (int s = 0; s < 5; ++s) B[s * Q3 + t] = v[s];
+            for (int s = 0; s < 5; ++s) B[s * BQ + pt] = v[s];
         }
         __syncthreads();
-        lds_pass<Q, Q, Q, 2, N, false>(B, A, mpi, 5);
+        lds_pass<Q, Q, Q, 2, N, false, XQ, XQ>(B, A, mpi, 5);
         __syncthreads();
-        lds_pass<Q, Q, N, 1, N, false>(A, B, mpi, 5);
+        lds_pass<Q, Q, N, 1, N, false, XQ, XQ>(A, B, mpi, 5);
         __syncthreads();
-        lds_pass<Q, N, N, 0, N, false>(B, A, mpi, 5);
+        lds_pass<Q, N, N, 0, N, false, XQ, XN>(B, A, mpi, 5);
         __syncthreads();
         for (int i = tid; i < 5 * N3; i += blockDim.x) {
             const int s = i / N3, nd = i - s * N3;
-            vhat[s * SE + e * N3 + nd] = A[i];
+            vhat[s * SE + e * N3 + nd] = A[s * BN + nd % N + XN * (nd / N)];
         }
     }
     // v^ (DG: u) at the face points: the end slab of the coefficients,
     // interpolated along the first and then the second tangential direction
-    gather_slabs<N>(A, SL, 1);
+    gather_slabs<N, XN, XN>(A, SL, 1);
     __syncthreads();
-    lds_pass<N, N, 1, 0, Q, false>(SL, T, mchi, 30);
+    lds_pass<N, N, 1, 0, Q, false, XN, XQ>(SL, T, mchi, 30);
     __syncthreads();
-    lds_pass<Q, N, 1, 1, Q, false>(T, SF, mchi, 30);
+    lds_pass<Q, N, 1, 1, Q, false, XQ, XQ>(T, SF, mchi, 30);
     __syncthreads();
     for (int it = tid; it < 30 * Q2; it += blockDim.x) {
         const int fs = it / Q2, t = it - fs * Q2;
-        ft[((int64_t)fs * E + e) * Q2 + t] = SF[it];
+        ft[((int64_t)fs * E + e) * Q2 + t] = SF[fs * (XQ * Q) + t % Q + XQ * (t / Q)];
     }
 }
 
@@ -920,7 +932,8 @@ static size_t gl_stage_lds(int p, int q) {
 }
 
 static size_t gl_project_lds(int p, int q) {
-    return (2 * q * (p + 1) + 10 * (size_t)q * q * q + slab_lds(p + 1, q)) * sizeof(double);
+    const int n = p + 1, xn = odd_pitch(n), xq = odd_pitch(q);   // row pitches of the kernel's LDS arrays
+    return (2 * q * n + 10 * (size_t)xq * q * q + 30 * (xn * n + xq * n + xq * q)) * sizeof(double);
 }
 
 size_t gl_lds_bytes(bool dg, int p, int q, int epb) {
