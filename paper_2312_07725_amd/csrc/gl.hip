@@ -48,8 +48,8 @@ constexpr int DG_BLOCK = 512;   // DG stage (3 q^2 <= 432 line threads at q = 12
 template <int S0, int S1, int S2, int AX, int OUT, bool TR, int SP = S0, int DP = (AX == 0 ? OUT : S0)>
 __device__ __forceinline__ void lds_pass(const double* __restrict__ src, double* __restrict__ dst,
                                          const double* __restrict__ M, int ns) {
-    // SP, DP: pitch of an x-row in src and dst (>= the row length; a pitch
-    // that is odd spreads the lanes of the x- and y-passes over the LDS banks)
+    // SP, DP: pitch of an x-row in src and dst (>= the row length; a padded
+    // pitch spreads the lanes of the x- and y-passes over the LDS banks)
     constexpr int IN = AX == 0 ? S0 : (AX == 1 ? S1 : S2);
     constexpr int D1 = AX == 1 ? OUT : S1, D2 = AX == 2 ? OUT : S2;
     constexpr int SRC = SP * S1 * S2, NL = S0 * S1 * S2 / IN, DST = DP * D1 * D2;
@@ -85,8 +85,12 @@ __device__ __forceinline__ void lds_pass(const double* __restrict__ src, double*
     }
 }
 
-// An odd x-row pitch for a row of n values (n itself when odd).
-__host__ __device__ constexpr int odd_pitch(int n) { return n | 1; }
+// x-row pitch for rows of n doubles: a length that is a multiple of 4 puts
+// the 16 lanes of an x-pass, which step through consecutive rows, on a
+// quarter of the LDS bank pairs or fewer, so such rows get one pad slot;
+// other lengths at most halve them and are left unpadded (the pad's index
+// arithmetic then costs more than it saves).
+__host__ __device__ constexpr int bank_pitch(int n) { return n % 4 == 0 ? n + 1 : n; }
 
 // Face slabs of a coefficient array X [nb][5][n^3] (nb element blocks): copy
 // the six end slabs into SL [nb][6][5][n^2] (tangential indices in increasing
@@ -108,22 +112,24 @@ __device__ __forceinline__ void gather_slabs(const double* __restrict__ X, doubl
 
 // Add the six face slabs FS [nb][6][5][n^2] onto the coefficient array X
 // [nb][5][n^3] (node-parallel: each node adds the slabs of the faces it lies on).
-template <int N>
+template <int N, int XP = N, int SLP = N>
 __device__ __forceinline__ void scatter_add_slabs(double* __restrict__ X, const double* __restrict__ FS, int nb) {
-    constexpr int N2 = N * N, N3 = N2 * N;
+    // XP: x-row pitch of X's blocks; SLP: pitch of a slab's first tangential row
+    constexpr int N2 = N * N, N3 = N2 * N, SB = SLP * N;
     for (int it = threadIdx.x; it < nb * 5 * N3; it += blockDim.x) {
         const int el = it / (5 * N3), r = it - el * 5 * N3;
         const int s = r / N3, nd = r - s * N3;
         const int a = nd % N, b = (nd / N) % N, c = nd / N2;
-        const double* fs = FS + el * 30 * N2 + s * N2;
-        double acc = X[it];
-        if (a == 0) acc += fs[0 * 5 * N2 + b + N * c];
-        if (a == N - 1) acc += fs[1 * 5 * N2 + b + N * c];
-        if (b == 0) acc += fs[2 * 5 * N2 + a + N * c];
-        if (b == N - 1) acc += fs[3 * 5 * N2 + a + N * c];
-        if (c == 0) acc += fs[4 * 5 * N2 + a + N * b];
-        if (c == N - 1) acc += fs[5 * 5 * N2 + a + N * b];
-        X[it] = acc;
+        const double* fs = FS + (el * 30 + s) * SB;
+        double* x = X + (el * 5 + s) * (XP * N2) + a + XP * (b + N * c);
+        double acc = *x;
+        if (a == 0) acc += fs[0 * 5 * SB + b + SLP * c];
+        if (a == N - 1) acc += fs[1 * 5 * SB + b + SLP * c];
+        if (b == 0) acc += fs[2 * 5 * SB + a + SLP * c];
+        if (b == N - 1) acc += fs[3 * 5 * SB + a + SLP * c];
+        if (c == 0) acc += fs[4 * 5 * SB + a + SLP * b];
+        if (c == N - 1) acc += fs[5 * 5 * SB + a + SLP * b];
+        *x = acc;
     }
 }
 
@@ -249,10 +255,18 @@ __global__ __launch_bounds__(GL_BLOCK) void gl_project_kernel(const GLOps* __res
                                                               const double* __restrict__ U, double gamma,
                                                               double* vhat, double* ft) {
     constexpr int N2 = N * N, N3 = N2 * N, Q2 = Q * Q, Q3 = Q2 * Q;
-    // x-row pitches of the LDS arrays (odd for the NSFR projection, so that the
-    // lanes of the x- and y-passes fall on different LDS banks)
-    constexpr int XN = DG ? N : odd_pitch(N), XQ = DG ? Q : odd_pitch(Q);
+    // x-row pitches of the LDS arrays (padded for the NSFR projection, so that
+    // the lanes of the x- and y-passes fall on different LDS banks)
+    constexpr int XN = DG ? N : bank_pitch(N), XQ = DG ? Q : bank_pitch(Q);
     constexpr int BN = XN * N2, BQ = XQ * Q2;   // block sizes of an n^3 and a q^3 array
+    auto pn = [](int nd) {   // node -> padded index (the identity without padding)
+        if constexpr (XN == N) return nd;
+        else return nd % N + XN * (nd / N);
+    };
+    auto pq = [](int t) {    // volume or face point (rows of q) -> padded index
+        if constexpr (XQ == Q) return t;
+        else return t % Q + XQ * (t / Q);
+    };
     extern __shared__ double lds[];
     constexpr int AS = DG ? 5 * N3 : 5 * BQ, BS = DG ? 0 : 5 * BQ;
     double* mchi = lds;              // Q x N
@@ -272,7 +286,7 @@ __global__ __launch_bounds__(GL_BLOCK) void gl_project_kernel(const GLOps* __res
     }
     for (int i = tid; i < 5 * N3; i += blockDim.x) {
         const int s = i / N3, nd = i - s * N3;
-        A[s * BN + nd % N + XN * (nd / N)] = U[s * SE + e * N3 + nd];
+        A[s * BN + pn(nd)] = U[s * SE + e * N3 + nd];
     }
     __syncthreads();
     if constexpr (!DG) {
@@ -283,7 +297,7 @@ __global__ __launch_bounds__(GL_BLOCK) void gl_project_kernel(const GLOps* __res
         lds_pass<Q, Q, N, 2, Q, false, XQ, XQ>(A, B, mchi, 5);
         __syncthreads();
         for (int t = tid; t < Q3; t += blockDim.x) {
-            const int pt = t % Q + XQ * (t / Q);
+            const int pt = pq(t);
             double u[5], v[5];
 #pragma unroll
             for (int s = 0; s < 5; ++s) u[s] = B[s * BQ + pt];
@@ -300,7 +314,7 @@ __global__ __launch_bounds__(GL_BLOCK) void gl_project_kernel(const GLOps* __res
         __syncthreads();
         for (int i = tid; i < 5 * N3; i += blockDim.x) {
             const int s = i / N3, nd = i - s * N3;
-            vhat[s * SE + e * N3 + nd] = A[s * BN + nd % N + XN * (nd / N)];
+            vhat[s * SE + e * N3 + nd] = A[s * BN + pn(nd)];
         }
     }
     // v^ (DG: u) at the face points: the end slab of the coefficients,
@@ -313,7 +327,7 @@ __global__ __launch_bounds__(GL_BLOCK) void gl_project_kernel(const GLOps* __res
     __syncthreads();
     for (int it = tid; it < 30 * Q2; it += blockDim.x) {
         const int fs = it / Q2, t = it - fs * Q2;
-        ft[((int64_t)fs * E + e) * Q2 + t] = SF[fs * (XQ * Q) + t % Q + XQ * (t / Q)];
+        ft[((int64_t)fs * E + e) * Q2 + t] = SF[fs * (XQ * Q) + pq(t)];
     }
 }
 
@@ -328,6 +342,18 @@ template <int N, int Q, int VARIANT>
 __global__ __launch_bounds__(GL_BLOCK) __attribute__((amdgpu_waves_per_eu(gl_stage_min_waves(Q))))
 void gl_stage_kernel(StageArgs A, GLArgs G) {
     constexpr int N2 = N * N, N3 = N2 * N, Q2 = Q * Q, Q3 = Q2 * Q;
+    // x-row pitches of the LDS arrays, so that lanes stepping through rows of
+    // n or q values fall on different LDS banks; block sizes of an n^3 and a
+    // q^3 array
+    constexpr int XN = bank_pitch(N), XQ = bank_pitch(Q), BN = XN * N2, BQ = XQ * Q2;
+    auto pn = [](int nd) {   // node -> padded index (the identity without padding)
+        if constexpr (XN == N) return nd;
+        else return nd % N + XN * (nd / N);
+    };
+    auto pq = [](int t) {    // volume point -> padded index
+        if constexpr (XQ == Q) return t;
+        else return t % Q + XQ * (t / Q);
+    };
     extern __shared__ double lds[];
     double* mchi = lds;               // Q x N
     double* mpit = mchi + Q * N;      // N x Q
@@ -335,10 +361,11 @@ void gl_stage_kernel(StageArgs A, GLArgs G) {
     double* mtl = msq + Q2;           // Q
     double* mtr = mtl + Q;            // Q
     double* mw = mtr + Q;             // Q
-    double* BA = mw + Q;              // 6 Q^3: pass buffer, then the volume primitives
-    double* BB = BA + 6 * Q3;         // 5 Q^3: pass buffer, then the volume residual
-    double* FP = BB + 5 * Q3;         // [6 faces][6][Q^2]: primitives at the own face points
-    double* RF = FP + 36 * Q2;        // [6 faces][5][Q^2]: face-point residuals
+    double* BA = mw + Q;              // 6 BQ: pass buffer, then the volume primitives
+    double* BB = BA + 6 * BQ;         // 5 BQ: pass buffer, then the volume residual
+    double* FP = BB + 5 * BQ;         // [6 faces][6][Q^2]: primitives at the own face points
+    double* RF = FP + 36 * Q2;        // [6 faces][5][Q^2]: face-point residuals (unpadded: the
+                                      // padded face arrays would cost the eighth workgroup per CU)
     double* TF = RF + 30 * Q2;        // [6 faces][5][Q N]: their first tangential contraction
     const int tid = threadIdx.x, nth = blockDim.x;
     const int64_t e = blockIdx.x;
@@ -360,7 +387,7 @@ void gl_stage_kernel(StageArgs A, GLArgs G) {
     // 1. v^ of this element -> volume points; own face points from the face traces
     for (int i = tid; i < 5 * N3; i += nth) {
         const int s = i / N3, nd = i - s * N3;
-        BA[i] = G.vhat[s * SE + e * N3 + nd];
+        BA[s * BN + pn(nd)] = G.vhat[s * SE + e * N3 + nd];
     }
     for (int it = tid; it < 6 * Q2; it += nth) {
         const int f = it / Q2, t = it - f * Q2;
@@ -377,23 +404,24 @@ void gl_stage_kernel(StageArgs A, GLArgs G) {
         L[5 * Q2] = q.beta;
     }
     __syncthreads();
-    lds_pass<N, N, N, 0, Q, false>(BA, BB, mchi, 5);
+    lds_pass<N, N, N, 0, Q, false, XN, XQ>(BA, BB, mchi, 5);
     __syncthreads();
-    lds_pass<Q, N, N, 1, Q, false>(BB, BA, mchi, 5);
+    lds_pass<Q, N, N, 1, Q, false, XQ, XQ>(BB, BA, mchi, 5);
     __syncthreads();
-    lds_pass<Q, Q, N, 2, Q, false>(BA, BB, mchi, 5);
+    lds_pass<Q, Q, N, 2, Q, false, XQ, XQ>(BA, BB, mchi, 5);
     __syncthreads();
     for (int t = tid; t < Q3; t += nth) {
+        const int pt = pq(t);
         double v[5];
 #pragma unroll
-        for (int s = 0; s < 5; ++s) v[s] = BB[s * Q3 + t];
+        for (int s = 0; s < 5; ++s) v[s] = BB[s * BQ + pt];
         const PrimR q = prims_from_entropy(v, gm1, gamma, pref);
-        BA[t] = q.rho;
-        BA[Q3 + t] = q.u;
-        BA[2 * Q3 + t] = q.v;
-        BA[3 * Q3 + t] = q.w;
-        BA[4 * Q3 + t] = q.pd;
-        BA[5 * Q3 + t] = q.beta;
+        BA[pt] = q.rho;
+        BA[BQ + pt] = q.u;
+        BA[2 * BQ + pt] = q.v;
+        BA[3 * BQ + pt] = q.w;
+        BA[4 * BQ + pt] = q.pd;
+        BA[5 * BQ + pt] = q.beta;
     }
     __syncthreads();
 
@@ -408,15 +436,16 @@ void gl_stage_kernel(StageArgs A, GLArgs G) {
     const int dir = active ? lt / Q2 : 0;
     const int l = active ? lt - dir * Q2 : 0;
     const int t1 = l % Q, t2 = l / Q;
-    const int base = dir == 0 ? Q * t1 + Q2 * t2 : (dir == 1 ? t1 + Q2 * t2 : t1 + Q * t2);
-    const int stride = dir == 0 ? 1 : (dir == 1 ? Q : Q2);
+    // the line's first point and point stride in the padded volume arrays
+    const int base = dir == 0 ? XQ * (t1 + Q * t2) : (dir == 1 ? t1 + XQ * Q * t2 : t1 + XQ * t2);
+    const int stride = dir == 0 ? 1 : (dir == 1 ? XQ : XQ * Q);
     const double wperp = mw[t1] * mw[t2];
     const double* Cl = G.geo.Cq + (int64_t)(3 * dir) * E * Q3 + e * Q3 + l;   // [comp][pos Q^2]
     const int64_t CS = E * Q3;
     const int64_t FS = E * Q2;
     auto volp = [&](int a) {
         const int t = base + a * stride;
-        return PrimR{BA[t], BA[Q3 + t], BA[2 * Q3 + t], BA[3 * Q3 + t], BA[4 * Q3 + t], BA[5 * Q3 + t]};
+        return PrimR{BA[t], BA[BQ + t], BA[2 * BQ + t], BA[3 * BQ + t], BA[4 * BQ + t], BA[5 * BQ + t]};
     };
     // the line's volume residual into BB: phase ph stores (first pass) or adds
     auto accumulate = [&](double (&Rv)[5][Q], bool first) {
@@ -427,7 +456,7 @@ void gl_stage_kernel(StageArgs A, GLArgs G) {
 #pragma unroll
                     for (int a = 0; a < Q; ++a) {
                         const double v = Rv[s][a] * wperp;
-                        double* x = BB + s * Q3 + base + a * stride;
+                        double* x = BB + s * BQ + base + a * stride;
                         if (first && ph == 0) *x = v;
                         else *x += v;
                     }
@@ -544,7 +573,7 @@ void gl_stage_kernel(StageArgs A, GLArgs G) {
             mms_source(X[0], X[EQ], X[2 * EQ], t, gamma, qs);
             const double wj = 1.0 / G.geo.invWJ[e * Q3 + p];
 #pragma unroll
-            for (int s = 0; s < 5; ++s) BB[s * Q3 + p] -= wj * qs[s];
+            for (int s = 0; s < 5; ++s) BB[s * BQ + pq(p)] -= wj * qs[s];
         }
     }
     __syncthreads();
@@ -553,43 +582,50 @@ void gl_stage_kernel(StageArgs A, GLArgs G) {
     //    the face residuals through the tangential chi^T onto the end slabs
     //    (the face residuals go through the tangential chi^T, RF -> TF -> RF as
     //    [6][5][N^2], alongside the first two volume passes)
-    lds_pass<Q, Q, Q, 2, N, true>(BB, BA, mchi, 5);
+    lds_pass<Q, Q, Q, 2, N, true, XQ, XQ>(BB, BA, mchi, 5);
     lds_pass<Q, Q, 1, 0, N, true>(RF, TF, mchi, 30);
     __syncthreads();
-    lds_pass<Q, Q, N, 1, N, true>(BA, BB, mchi, 5);
+    lds_pass<Q, Q, N, 1, N, true, XQ, XQ>(BA, BB, mchi, 5);
     lds_pass<N, Q, 1, 1, N, true>(TF, RF, mchi, 30);
     __syncthreads();
-    lds_pass<Q, N, N, 0, N, true>(BB, BA, mchi, 5);
+    lds_pass<Q, N, N, 0, N, true, XQ, XN>(BB, BA, mchi, 5);
     __syncthreads();
-    scatter_add_slabs<N>(BA, RF, 1);
+    scatter_add_slabs<N, XN, N>(BA, RF, 1);
     __syncthreads();
     if (mode == MODE_RESIDUAL) {
         for (int it = tid; it < 5 * N3; it += nth) {
             const int s = it / N3, nd = it - s * N3;
-            A.out[s * SE + e * N3 + nd] = BA[it];
+            A.out[s * SE + e * N3 + nd] = BA[s * BN + pn(nd)];
         }
         return;
     }
     // 4. weight-adjusted inverse: Pi~^T (coefficients -> points), (W J)^-1, Pi~
-    lds_pass<N, N, N, 0, Q, true>(BA, BB, mpit, 5);
+    lds_pass<N, N, N, 0, Q, true, XN, XQ>(BA, BB, mpit, 5);
     __syncthreads();
-    lds_pass<Q, N, N, 1, Q, true>(BB, BA, mpit, 5);
+    lds_pass<Q, N, N, 1, Q, true, XQ, XQ>(BB, BA, mpit, 5);
     __syncthreads();
-    lds_pass<Q, Q, N, 2, Q, true>(BA, BB, mpit, 5);
+    lds_pass<Q, Q, N, 2, Q, true, XQ, XQ>(BA, BB, mpit, 5);
     __syncthreads();
-    for (int it = tid; it < 5 * Q3; it += nth) BB[it] *= G.geo.invWJ[e * Q3 + it % Q3];
+    for (int it = tid; it < 5 * Q3; it += nth) {
+        if constexpr (XQ == Q) {
+            BB[it] *= G.geo.invWJ[e * Q3 + it % Q3];
+        } else {
+            const int s = it / Q3, t = it - s * Q3;
+            BB[s * BQ + pq(t)] *= G.geo.invWJ[e * Q3 + t];
+        }
+    }
     __syncthreads();
-    lds_pass<Q, Q, Q, 2, N, false>(BB, BA, mpit, 5);
+    lds_pass<Q, Q, Q, 2, N, false, XQ, XQ>(BB, BA, mpit, 5);
     __syncthreads();
-    lds_pass<Q, Q, N, 1, N, false>(BA, BB, mpit, 5);
+    lds_pass<Q, Q, N, 1, N, false, XQ, XQ>(BA, BB, mpit, 5);
     __syncthreads();
-    lds_pass<Q, N, N, 0, N, false>(BB, BA, mpit, 5);
+    lds_pass<Q, N, N, 0, N, false, XQ, XN>(BB, BA, mpit, 5);
     __syncthreads();
     // 5. RK combination
     for (int it = tid; it < 5 * N3; it += nth) {
         const int s = it / N3, nd = it - s * N3;
         const int64_t gi = s * SE + e * N3 + nd;
-        const double k = -BA[it];
+        const double k = -BA[s * BN + pn(nd)];
         switch (mode) {
             case MODE_RHS: A.out[gi] = k; break;
             case MODE_RK1: {
@@ -927,12 +963,13 @@ static size_t dg_project_lds(int p, int q) {
 }
 
 static size_t gl_stage_lds(int p, int q) {
-    const int n = p + 1;
-    return (size_t)(2 * q * n + q * q + 3 * q + 11 * q * q * q + 66 * q * q + 30 * q * n) * sizeof(double);
+    const int n = p + 1, xn = bank_pitch(n), xq = bank_pitch(q);   // row pitches of the kernel's LDS arrays
+    (void)xn;
+    return (size_t)(2 * q * n + q * q + 3 * q + 11 * xq * q * q + 66 * q * q + 30 * q * n) * sizeof(double);
 }
 
 static size_t gl_project_lds(int p, int q) {
-    const int n = p + 1, xn = odd_pitch(n), xq = odd_pitch(q);   // row pitches of the kernel's LDS arrays
+    const int n = p + 1, xn = bank_pitch(n), xq = bank_pitch(q);   // row pitches of the kernel's LDS arrays
     return (2 * q * n + 10 * (size_t)xq * q * q + 30 * (xn * n + xq * n + xq * q)) * sizeof(double);
 }
 
