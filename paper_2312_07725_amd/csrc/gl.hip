@@ -92,6 +92,16 @@ __device__ __forceinline__ void lds_pass(const double* __restrict__ src, double*
 // arithmetic then costs more than it saves).
 __host__ __device__ constexpr int bank_pitch(int n) { return n % 4 == 0 ? n + 1 : n; }
 
+// LDS doubles of the DG stage kernel for epb elements with volume row pitch
+// xq, and the pitch it uses: padded unless that would not fit one element in
+// gfx950's 160 KiB of LDS per workgroup (p = 5 with 12 points).
+__host__ __device__ constexpr int dg_stage_doubles(int n, int q, int xq, int epb) {
+    return 2 * q * n + q * q + 3 * q + epb * (5 * xq * q * q + 5 * xq * q * n + 30 * q * q + 30 * q * n);
+}
+__host__ __device__ constexpr int dg_row_pitch(int n, int q) {
+    return dg_stage_doubles(n, q, bank_pitch(q), 1) * 8 <= 160 * 1024 ? bank_pitch(q) : q;
+}
+
 // Face slabs of a coefficient array X [nb][5][n^3] (nb element blocks): copy
 // the six end slabs into SL [nb][6][5][n^2] (tangential indices in increasing
 // direction order, first fastest).
@@ -727,6 +737,17 @@ __device__ __forceinline__ void roe_flux_dev(const double A[5], const double B[5
 template <int N, int Q>
 __global__ __launch_bounds__(DG_BLOCK) void dg_stage_kernel(StageArgs A, GLArgs G) {
     constexpr int N2 = N * N, N3 = N2 * N, Q2 = Q * Q, Q3 = Q2 * Q, L3 = 3 * Q2;
+    // x-row pitches of the volume arrays (bank spread, as in the NSFR kernels)
+    // and the block sizes of an n^3 and a q^3 array
+    constexpr int XQ = dg_row_pitch(N, Q), XN = XQ == Q ? N : bank_pitch(N), BN = XN * N2, BQ = XQ * Q2;
+    auto pn = [](int nd) {   // node -> padded index (the identity without padding)
+        if constexpr (XN == N) return nd;
+        else return nd % N + XN * (nd / N);
+    };
+    auto pq = [](int t) {    // volume point -> padded index
+        if constexpr (XQ == Q) return t;
+        else return t % Q + XQ * (t / Q);
+    };
     extern __shared__ double lds[];
     const int epb = A.epb;
     double* mchi = lds;               // Q x N
@@ -735,9 +756,9 @@ __global__ __launch_bounds__(DG_BLOCK) void dg_stage_kernel(StageArgs A, GLArgs 
     double* mtl = mdq + Q2;           // Q
     double* mtr = mtl + Q;            // Q
     double* mw = mtr + Q;             // Q
-    double* VA = mw + Q;              // epb 5 Q^3
-    double* VB = VA + epb * 5 * Q3;   // epb 5 Q^2 N
-    double* RF = VB + epb * 5 * Q2 * N;   // epb [6][5][Q^2]
+    double* VA = mw + Q;              // epb 5 BQ
+    double* VB = VA + epb * 5 * BQ;   // epb 5 XQ Q N
+    double* RF = VB + epb * 5 * XQ * Q * N;   // epb [6][5][Q^2]
     double* TF = RF + epb * 30 * Q2;      // epb [6][5][Q N]
     const int tid = threadIdx.x, nth = blockDim.x;
     const int64_t E = A.geo.E;
@@ -762,14 +783,14 @@ __global__ __launch_bounds__(DG_BLOCK) void dg_stage_kernel(StageArgs A, GLArgs 
     for (int i = tid; i < epb * 5 * N3; i += nth) {
         const int el = i / (5 * N3), r = i - el * 5 * N3;
         const int s = r / N3, nd = r - s * N3;
-        VB[i] = el < nel ? A.Uin[s * SE + (e0 + el) * N3 + nd] : 0.0;
+        VB[(el * 5 + s) * BN + pn(nd)] = el < nel ? A.Uin[s * SE + (e0 + el) * N3 + nd] : 0.0;
     }
     __syncthreads();
-    lds_pass<N, N, N, 0, Q, false>(VB, VA, mchi, 5 * epb);
+    lds_pass<N, N, N, 0, Q, false, XN, XQ>(VB, VA, mchi, 5 * epb);
     __syncthreads();
-    lds_pass<Q, N, N, 1, Q, false>(VA, VB, mchi, 5 * epb);
+    lds_pass<Q, N, N, 1, Q, false, XQ, XQ>(VA, VB, mchi, 5 * epb);
     __syncthreads();
-    lds_pass<Q, Q, N, 2, Q, false>(VB, VA, mchi, 5 * epb);
+    lds_pass<Q, Q, N, 2, Q, false, XQ, XQ>(VB, VA, mchi, 5 * epb);
     __syncthreads();
 
     // 2. one thread per (element, line): the contravariant flux f^r_k at the
@@ -783,9 +804,10 @@ __global__ __launch_bounds__(DG_BLOCK) void dg_stage_kernel(StageArgs A, GLArgs 
     const int l = lt - dir * Q2;
     const int64_t e = e0 + (active ? el : 0);
     const int t1 = l % Q, t2 = l / Q;
-    const int base = dir == 0 ? Q * t1 + Q2 * t2 : (dir == 1 ? t1 + Q2 * t2 : t1 + Q * t2);
-    const int stride = dir == 0 ? 1 : (dir == 1 ? Q : Q2);
-    double* va = VA + (active ? el : 0) * 5 * Q3;
+    // the line's first point and point stride in the padded volume arrays
+    const int base = dir == 0 ? XQ * (t1 + Q * t2) : (dir == 1 ? t1 + XQ * Q * t2 : t1 + XQ * t2);
+    const int stride = dir == 0 ? 1 : (dir == 1 ? XQ : XQ * Q);
+    double* va = VA + (active ? el : 0) * 5 * BQ;
     const double wperp = mw[t1] * mw[t2];
     // (a) the flux-basis derivative along the line and the line's end values of
     //     f^r_k; the volume part into VA in a fixed direction order
@@ -804,8 +826,8 @@ __global__ __launch_bounds__(DG_BLOCK) void dg_stage_kernel(StageArgs A, GLArgs 
 #pragma unroll
             for (int b = 0; b < Q; ++b) {
                 const int t = base + b * stride;
-                const double r = va[t], m1 = va[Q3 + t], m2 = va[2 * Q3 + t], m3 = va[3 * Q3 + t],
-                             en = va[4 * Q3 + t];
+                const double r = va[t], m1 = va[BQ + t], m2 = va[2 * BQ + t], m3 = va[3 * BQ + t],
+                             en = va[4 * BQ + t];
                 const double cx = Cl[b * Q2], cy = Cl[CS + b * Q2], cz = Cl[2 * CS + b * Q2];
                 const double ir = 1.0 / r;
                 const double unb = (m1 * cx + m2 * cy + m3 * cz) * ir;
@@ -830,7 +852,7 @@ __global__ __launch_bounds__(DG_BLOCK) void dg_stage_kernel(StageArgs A, GLArgs 
 #pragma unroll
                     for (int a = 0; a < Q; ++a) {
                         const double v = Rv[s][a] * (mw[a] * wperp);
-                        double* x = va + s * Q3 + base + a * stride;
+                        double* x = va + s * BQ + base + a * stride;
                         if (ph == 0) *x = v;
                         else *x += v;
                     }
@@ -880,53 +902,54 @@ __global__ __launch_bounds__(DG_BLOCK) void dg_stage_kernel(StageArgs A, GLArgs 
             mms_source(X[0], X[EQ], X[2 * EQ], t, gamma, qs);
             const double wj = 1.0 / G.geo.invWJ[(e0 + ei) * Q3 + p];
 #pragma unroll
-            for (int s = 0; s < 5; ++s) VA[(ei * 5 + s) * Q3 + p] -= wj * qs[s];
+            for (int s = 0; s < 5; ++s) VA[(ei * 5 + s) * BQ + pq(p)] -= wj * qs[s];
         }
     }
     __syncthreads();
     // 3. chi^T along z, y, x (VA -> VB -> VA -> VB), face residuals onto the end slabs
-    lds_pass<Q, Q, Q, 2, N, true>(VA, VB, mchi, 5 * epb);
+    lds_pass<Q, Q, Q, 2, N, true, XQ, XQ>(VA, VB, mchi, 5 * epb);
     lds_pass<Q, Q, 1, 0, N, true>(RF, TF, mchi, 30 * epb);
     __syncthreads();
-    lds_pass<Q, Q, N, 1, N, true>(VB, VA, mchi, 5 * epb);
+    lds_pass<Q, Q, N, 1, N, true, XQ, XQ>(VB, VA, mchi, 5 * epb);
     lds_pass<N, Q, 1, 1, N, true>(TF, RF, mchi, 30 * epb);
     __syncthreads();
-    lds_pass<Q, N, N, 0, N, true>(VA, VB, mchi, 5 * epb);
+    lds_pass<Q, N, N, 0, N, true, XQ, XN>(VA, VB, mchi, 5 * epb);
     __syncthreads();
-    scatter_add_slabs<N>(VB, RF, epb);
+    scatter_add_slabs<N, XN, N>(VB, RF, epb);
     __syncthreads();
     if (mode == MODE_RESIDUAL) {
         for (int it = tid; it < nel * 5 * N3; it += nth) {
             const int ei = it / (5 * N3), r0 = it - ei * 5 * N3;
             const int s = r0 / N3, nd = r0 - s * N3;
-            A.out[s * SE + (e0 + ei) * N3 + nd] = VB[it];
+            A.out[s * SE + (e0 + ei) * N3 + nd] = VB[(ei * 5 + s) * BN + pn(nd)];
         }
         return;
     }
     // 4. weight-adjusted inverse: Pi~^T (VB -> VA -> VB -> VA), 1 / (W J), Pi~ (VA -> VB -> VA -> VB)
-    lds_pass<N, N, N, 0, Q, true>(VB, VA, mpit, 5 * epb);
+    lds_pass<N, N, N, 0, Q, true, XN, XQ>(VB, VA, mpit, 5 * epb);
     __syncthreads();
-    lds_pass<Q, N, N, 1, Q, true>(VA, VB, mpit, 5 * epb);
+    lds_pass<Q, N, N, 1, Q, true, XQ, XQ>(VA, VB, mpit, 5 * epb);
     __syncthreads();
-    lds_pass<Q, Q, N, 2, Q, true>(VB, VA, mpit, 5 * epb);
+    lds_pass<Q, Q, N, 2, Q, true, XQ, XQ>(VB, VA, mpit, 5 * epb);
     __syncthreads();
     for (int it = tid; it < nel * 5 * Q3; it += nth) {
         const int ei = it / (5 * Q3), t = it % Q3;
-        VA[it] *= G.geo.invWJ[(e0 + ei) * Q3 + t];
+        if constexpr (XQ == Q) VA[it] *= G.geo.invWJ[(e0 + ei) * Q3 + t];
+        else VA[(it / Q3) * BQ + pq(t)] *= G.geo.invWJ[(e0 + ei) * Q3 + t];
     }
     __syncthreads();
-    lds_pass<Q, Q, Q, 2, N, false>(VA, VB, mpit, 5 * epb);
+    lds_pass<Q, Q, Q, 2, N, false, XQ, XQ>(VA, VB, mpit, 5 * epb);
     __syncthreads();
-    lds_pass<Q, Q, N, 1, N, false>(VB, VA, mpit, 5 * epb);
+    lds_pass<Q, Q, N, 1, N, false, XQ, XQ>(VB, VA, mpit, 5 * epb);
     __syncthreads();
-    lds_pass<Q, N, N, 0, N, false>(VA, VB, mpit, 5 * epb);
+    lds_pass<Q, N, N, 0, N, false, XQ, XN>(VA, VB, mpit, 5 * epb);
     __syncthreads();
     // 5. RK combination
     for (int it = tid; it < nel * 5 * N3; it += nth) {
         const int ei = it / (5 * N3), r0 = it - ei * 5 * N3;
         const int s = r0 / N3, nd = r0 - s * N3;
         const int64_t gi = s * SE + (e0 + ei) * N3 + nd;
-        const double k = -VB[it];
+        const double k = -VB[(ei * 5 + s) * BN + pn(nd)];
         switch (mode) {
             case MODE_RHS: A.out[gi] = k; break;
             case MODE_RK1: {
@@ -949,8 +972,7 @@ __global__ __launch_bounds__(DG_BLOCK) void dg_stage_kernel(StageArgs A, GLArgs 
 
 static size_t dg_stage_lds(int p, int q, int epb) {
     const int n = p + 1;
-    return (size_t)(2 * q * n + q * q + 3 * q + epb * (5 * q * q * q + 5 * q * q * n + 30 * q * q + 30 * q * n)) *
-           sizeof(double);
+    return (size_t)dg_stage_doubles(n, q, dg_row_pitch(n, q), epb) * sizeof(double);
 }
 
 // the projection kernels: operators, state buffers, and the face-slab
