@@ -315,12 +315,17 @@ __device__ __forceinline__ void line_geometry(int dir, int l, int& base, int& st
     else { base = t1 + N * t2; stride = N * N; }
 }
 
-// LDS index of a node in a padded node block: one pad slot after every
-// xi-row, so that the strided accesses of eta- and zeta-lines spread over the
-// LDS banks. A padded block holds N^3 + N^2 doubles.
+// LDS index of a node in a padded node block. For even N one pad slot
+// follows every xi-row, so that the lanes of a wave, which own consecutive
+// lines and read the same position along them, spread over the LDS banks (a
+// row stride of an even number of doubles would fold them onto a fraction of
+// the banks); an odd N already spreads them and is not padded (measured: the
+// pad cost 7% at p = 2 and 4). A padded block holds N^3 + N^2 doubles for
+// every N.
 template <int N>
 __device__ __forceinline__ int pad_node(int node) {
-    return node + node / N;
+    if constexpr (N % 2 == 1) return node;
+    else return node + node / N;
 }
 template <int N>
 constexpr int padded_block() {
