@@ -17,7 +17,9 @@
  *     face nodes, lifted by the
  *     FR-modified mass (Eq. NSFR, last term; Sec. 3.2);
  *   - mass: weight-adjusted inverse Pi~ (W J)^-1 Pi~^T of the FR-modified mass
- *     (Eq. weight-adj ESFR mass, Eq. Fr projection);
+ *     (Eq. weight-adj ESFR mass, Eq. Fr projection); optionally (config mass
+ *     = 1, nsfr_rhs only) the exact inverse of M_m + K_m (Eq. Km), factorised
+ *     per element at nsfr_create, for checking the weight-adjusted one;
  *   - time: four-stage fourth-order RK, read as classical RK4 (Sec. 7, opening
  *     paragraph).
  *
@@ -28,7 +30,8 @@
  *
  * Ownership. The caller allocates and owns every array passed in. The library
  * owns what it allocates in nsfr_create (operators, metrics, a residual-sized
- * workspace) and frees it in nsfr_destroy. nsfr_rhs, nsfr_residual,
+ * workspace; with mass = 1 the per-element mass factors) and frees it in
+ * nsfr_destroy. nsfr_rhs, nsfr_residual,
  * nsfr_rk4_step, nsfr_rk4_run and nsfr_rhs_vjp allocate nothing.
  *
  * Streams. All work is enqueued asynchronously on the context's HIP stream
