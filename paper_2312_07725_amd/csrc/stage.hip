@@ -27,11 +27,8 @@ namespace nsfr {
 constexpr int STAGE_BLOCK_MAX = 512;
 
 // Accumulator layout after the line sweep: per element three slots (one per
-// line direction) of [5][SPN] (padded node index; SPN = N^3 + N^2 + 1, one
-// more than the padded block, so that the five states of a slot start on
-// different LDS banks and the plane passes, whose lanes read the same node of
-// different (state, plane) blocks, do not conflict), EBLK = 3 SLOT doubles per
-// element.
+// line direction) of [5][SPN] (padded node index; SPN = slot_stride(N)),
+// EBLK = acc_elem_stride(N) >= 3 SLOT doubles per element.
 //
 // The weight-adjusted inverse Pi~ (W J)^-1 Pi~^T with Pi~ = P (x) P (x) P,
 // P = I - pia pib^T applied along a line as x <- x - pia (pib . x) (and P^T
@@ -44,9 +41,9 @@ constexpr int STAGE_BLOCK_MAX = 512;
 // zeta-plane) of the workgroup: w <- w - vec (coef . w) on each xi-row, then
 // on each eta-column. With SUM the input is the sum of the three direction
 // slots (fixed order) and the result goes to slot 0.
-template <int N, int SPN, bool SUM>
+template <int N, int SPN, int EBLK, bool SUM>
 __device__ __forceinline__ void plane_pass(double* lr, int epb, const double* coef, const double* vec) {
-    constexpr int N2 = N * N, SLOT = 5 * SPN, EBLK = 3 * SLOT;
+    constexpr int N2 = N * N, SLOT = 5 * SPN;
     for (int it = threadIdx.x; it < epb * 5 * N; it += blockDim.x) {
         const int k = it % N, sl = it / N;   // zeta plane; element * 5 + state
         const int eli = sl / 5, st = sl - eli * 5;
@@ -87,10 +84,10 @@ __device__ __forceinline__ void plane_pass(double* lr, int epb, const double* co
 // threads as item tid + j * nth, j < 2 (nth >= epb * 3 N^2 covers them in
 // two rounds); iw[j] holds 1/(W J) at item j's nodes, prefetched by the
 // caller.
-template <int N, int SPN>
+template <int N, int SPN, int EBLK>
 __device__ __forceinline__ void zeta_pass(double* lr, int epb, const double (&iw)[2][N], const double* pia,
                                           const double* pib) {
-    constexpr int N2 = N * N, SLOT = 5 * SPN, EBLK = 3 * SLOT;
+    constexpr int N2 = N * N;
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
         const int it = threadIdx.x + j * blockDim.x;
@@ -125,12 +122,29 @@ __device__ __forceinline__ void zeta_pass(double* lr, int epb, const double (&iw
 // the column in registers measured slightly faster.
 __host__ __device__ constexpr bool metric_in_lds(int p) { return p == 3; }
 
+// State stride (doubles) of an accumulator slot. The lanes of a plane pass
+// read the same node of consecutive (zeta plane, state) blocks, at LDS
+// addresses N^2 k + SPN s (N^2 padded to N^2 + N for even N); the 16 lanes
+// that share the 32 four-byte banks in one cycle of a 64-bit access spread
+// over all 16 bank pairs when these addresses differ mod 16. One more than the
+// padded block (N^3 + N^2 + 1) does that for N = 3, 4, 6; for N = 5 it (151)
+// folds the lanes onto 8 bank pairs and 141 spreads them (the unpadded
+// N = 5 block needs 125).
+__host__ __device__ constexpr int slot_stride(int n) { return n == 5 ? 141 : n * n * n + n * n + 1; }
+
+// Element stride (doubles) of the accumulator: the three slots, plus a pad
+// where the 5 N items of an element's plane pass (not a multiple of 16) let a
+// 16-lane group straddle two elements: 2 doubles at N = 4 and 14 at N = 5 put
+// the second element's blocks on the bank pairs the first leaves free (the
+// tile limits stay 6 and 3).
+__host__ __device__ constexpr int acc_elem_stride(int n) { return 15 * slot_stride(n) + (n == 4 ? 2 : n == 5 ? 14 : 0); }
+
 // LDS per element (doubles): during the sweep the primitives [6][PN3]
 // (padded) and at p = 3 the metric columns [9][N3]; afterwards the three
-// direction slots [3][5][SPN] of the accumulator.
+// direction slots [3][5][slot_stride] of the accumulator.
 __host__ __device__ constexpr int stage_lds_per_elem(int n) {
     const int sweep = 6 * (n * n * n + n * n) + (metric_in_lds(n - 1) ? 9 * n * n * n : 0);
-    const int acc = 15 * (n * n * n + n * n + 1);
+    const int acc = acc_elem_stride(n);
     return sweep > acc ? sweep : acc;
 }
 
@@ -142,8 +156,9 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
     constexpr int N = P + 1, N2 = N * N, N3 = N2 * N, LINES = 3 * N2;
     constexpr int PN3 = padded_block<N>();          // padded stride of a primitive component
     constexpr bool MLDS = metric_in_lds(P);
-    constexpr int SPN = PN3 + 1;                      // state stride of an accumulator slot
-    constexpr int SLOT = 5 * SPN, EBLK = 3 * SLOT;    // direction slots of the accumulator
+    constexpr int SPN = slot_stride(N);              // state stride of an accumulator slot
+    static_assert(SPN >= (N % 2 ? N3 : PN3), "a slot state must hold the (padded) node block");
+    constexpr int SLOT = 5 * SPN, EBLK = acc_elem_stride(N);   // direction slots of the accumulator
     constexpr int LDSE = stage_lds_per_elem(N);         // LDS doubles per element
     const int tid = threadIdx.x, nth = blockDim.x;
     const int epb = A.epb;
@@ -408,11 +423,11 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
         return;
     }
     if (CWA) {
-        plane_pass<N, SPN, true>(lr, epb, A.ops.pia, A.ops.pib);   // sum of the slots, P^T along xi, eta
+        plane_pass<N, SPN, EBLK, true>(lr, epb, A.ops.pia, A.ops.pib);   // sum of the slots, P^T along xi, eta
         __syncthreads();
-        zeta_pass<N, SPN>(lr, epb, zw, A.ops.pia, A.ops.pib);   // P^T, 1/(W J), P along zeta
+        zeta_pass<N, SPN, EBLK>(lr, epb, zw, A.ops.pia, A.ops.pib);   // P^T, 1/(W J), P along zeta
         __syncthreads();
-        plane_pass<N, SPN, false>(lr, epb, A.ops.pib, A.ops.pia);   // P along xi, eta
+        plane_pass<N, SPN, EBLK, false>(lr, epb, A.ops.pib, A.ops.pia);   // P along xi, eta
         __syncthreads();
     }
 #pragma unroll
