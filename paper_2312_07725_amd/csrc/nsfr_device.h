@@ -323,9 +323,21 @@ __device__ __forceinline__ void line_geometry(int dir, int l, int& base, int& st
 // pad cost 7% at p = 2 and 4). A padded block holds N^3 + N^2 doubles for
 // every N.
 template <int N>
-__device__ __forceinline__ int pad_node(int node) {
+__device__ __forceinline__ int pad_node(int node) {   // node >= 0
     if constexpr (N % 2 == 1) return node;
-    else return node + node / N;
+    else return node + (int)((unsigned)node / N);
+}
+// Length of a padded xi-row.
+template <int N>
+constexpr int padded_row() {
+    return N % 2 == 1 ? N : N + 1;
+}
+// Padded-index step along a line of direction dir (xi, eta, zeta): a row's pad
+// slot is passed at every eta or zeta step and at no xi step, so the padded
+// index of node a of the line base + a stride is pad_node(base) + a times this.
+template <int N>
+__device__ __forceinline__ int padded_stride(int dir) {
+    return dir == 0 ? 1 : (dir == 1 ? padded_row<N>() : padded_row<N>() * N);
 }
 template <int N>
 constexpr int padded_block() {

@@ -47,13 +47,14 @@ __device__ __forceinline__ void plane_pass(double* lr, int epb, const double* co
     for (int it = threadIdx.x; it < epb * 5 * N; it += blockDim.x) {
         const int k = it % N, sl = it / N;   // zeta plane; element * 5 + state
         const int eli = sl / 5, st = sl - eli * 5;
-        double* x = lr + eli * EBLK + st * SPN;
+        double* x = lr + eli * EBLK + st * SPN + pad_node<N>(N2 * k);   // the plane's first node
+        constexpr int R = padded_row<N>();
         double w[N][N];   // [eta][xi]
 #pragma unroll
         for (int j = 0; j < N; ++j)
 #pragma unroll
             for (int i = 0; i < N; ++i) {
-                const int pn = pad_node<N>(i + N * j + N2 * k);
+                const int pn = i + R * j;
                 w[j][i] = SUM ? (x[pn] + x[SLOT + pn]) + x[2 * SLOT + pn] : x[pn];
             }
 #pragma unroll
@@ -75,7 +76,7 @@ __device__ __forceinline__ void plane_pass(double* lr, int epb, const double* co
 #pragma unroll
         for (int j = 0; j < N; ++j)
 #pragma unroll
-            for (int i = 0; i < N; ++i) x[pad_node<N>(i + N * j + N2 * k)] = w[j][i];
+            for (int i = 0; i < N; ++i) x[i + R * j] = w[j][i];
     }
 }
 
@@ -94,12 +95,13 @@ __device__ __forceinline__ void zeta_pass(double* lr, int epb, const double (&iw
         if (it >= epb * 5 * N2) break;
         const int l = it % N2, sl = it / N2;   // zeta line (base l, stride N^2); element * 5 + state
         const int eli = sl / 5, st = sl - eli * 5;
-        double* x = lr + eli * EBLK + st * SPN;
+        double* x = lr + eli * EBLK + st * SPN + pad_node<N>(l);   // the line's first node
+        constexpr int RN = padded_row<N>() * N;                         // padded zeta step
         double v[N];
         double t = 0.0;
 #pragma unroll
         for (int a = 0; a < N; ++a) {
-            v[a] = x[pad_node<N>(l + a * N2)];
+            v[a] = x[a * RN];
             t += pia[a] * v[a];
         }
 #pragma unroll
@@ -108,7 +110,7 @@ __device__ __forceinline__ void zeta_pass(double* lr, int epb, const double (&iw
 #pragma unroll
         for (int a = 0; a < N; ++a) t += pib[a] * v[a];
 #pragma unroll
-        for (int a = 0; a < N; ++a) x[pad_node<N>(l + a * N2)] = v[a] - pia[a] * t;
+        for (int a = 0; a < N; ++a) x[a * RN] = v[a] - pia[a] * t;
     }
 }
 
@@ -227,6 +229,7 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
     // jump and always loads.
     int base, stride;
     line_geometry<N>(dir, l, base, stride);
+    const int pbase = pad_node<N>(base), pstride = padded_stride<N>(dir);   // the line in the LDS node index
     double fU[2][5], fC[2][3], oU[2][5];
     int fin[2] = {-1, -1};
     if (active) {
@@ -292,9 +295,9 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
             const double sg = side ? 0.5 : -0.5;   // outward reference normal / 2
             const int anbr = side ? 0 : N - 1;
             const PrimR qn = fin[side] >= 0
-                                 ? lds_primr<PN3>(lds + fin[side] * LDSE, pad_node<N>(base + anbr * stride))
+                                 ? lds_primr<PN3>(lds + fin[side] * LDSE, pbase + anbr * pstride)
                                  : primitives_ref(fU[side][0], fU[side][1], fU[side][2], fU[side][3], fU[side][4], gm1, pref);
-            const PrimR qo = lds_primr<PN3>(Lp, pad_node<N>(base + aown * stride));
+            const PrimR qo = lds_primr<PN3>(Lp, pbase + aown * pstride);
             const double nx = sg * (cmet(0, aown) + fC[side][0]), ny = sg * (cmet(1, aown) + fC[side][1]),
                          nz = sg * (cmet(2, aown) + fC[side][2]);
             double F[5];
@@ -307,11 +310,11 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
         // volume pairs of the line
 #pragma unroll
         for (int a = 0; a < N - 1; ++a) {
-            const PrimR qa = lds_primr<PN3>(Lp, pad_node<N>(base + a * stride));
+            const PrimR qa = lds_primr<PN3>(Lp, pbase + a * pstride);
             const double cax = cmet(0, a), cay = cmet(1, a), caz = cmet(2, a);
 #pragma unroll
             for (int b = a + 1; b < N; ++b) {
-                const PrimR qb = lds_primr<PN3>(Lp, pad_node<N>(base + b * stride));
+                const PrimR qb = lds_primr<PN3>(Lp, pbase + b * pstride);
                 const double cbx = cmet(0, b), cby = cmet(1, b), cbz = cmet(2, b);
                 double F[5];
                 // direction C(a) + C(b) = 2 N; the 1/2 is folded into S1h
@@ -378,7 +381,7 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
 #pragma unroll
         for (int s = 0; s < 5; ++s)
 #pragma unroll
-            for (int a = 0; a < N; ++a) x[s * SPN + pad_node<N>(base + a * stride)] = R[s][a] * wperp;
+            for (int a = 0; a < N; ++a) x[s * SPN + pbase + a * pstride] = R[s][a] * wperp;
     }
     __syncthreads();
     // residual of (element, state, node): the three directions summed in a fixed order

@@ -277,13 +277,14 @@ __global__ __launch_bounds__(VJP_BLOCK_MAX) void vjp_kernel(StageArgs A, const d
         const int l = dir == 0 ? j + N * k : (dir == 1 ? i + N * k : i + N * j);
         const int stride = dir == 0 ? 1 : (dir == 1 ? N : N2);
         const int base = node - a * stride;
+        const int pbase = pad_node<N>(base), pstride = padded_stride<N>(dir);   // the line in the LDS node index
         const double* Lc = Lp + 6 * PN3 + 3 * dir * N3 + l;
         const double cax = Lc[a * N2], cay = Lc[N3 + a * N2], caz = Lc[2 * N3 + a * N2];
         double Gd[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll 1
         for (int b = 0; b < N; ++b) {
             if (b == a) continue;
-            const int pb = pad_node<N>(base + b * stride);
+            const int pb = pbase + b * pstride;
             const Prim qb = lds_prim<PN3>(Lp, pb);
             const double sab = sS1h[a][b];
             double dl[5];
