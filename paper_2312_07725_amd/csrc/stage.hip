@@ -126,12 +126,14 @@ __host__ __device__ constexpr bool metric_in_lds(int p) { return p == 3; }
 
 // State stride (doubles) of an accumulator slot. The lanes of a plane pass
 // read the same node of consecutive (zeta plane, state) blocks, at LDS
-// addresses N^2 k + SPN s (N^2 padded to N^2 + N for even N); the 16 lanes
-// that share the 32 four-byte banks in one cycle of a 64-bit access spread
-// over all 16 bank pairs when these addresses differ mod 16. One more than the
-// padded block (N^3 + N^2 + 1) does that for N = 3, 4, 6; for N = 5 it (151)
-// folds the lanes onto 8 bank pairs and 141 spreads them (the unpadded
-// N = 5 block needs 125).
+// addresses N^2 k + SPN s (N^2 padded to N^2 + N for even N). In a model of
+// the LDS as 32 four-byte banks serving a 64-bit access 16 lanes at a time
+// (it reproduces the bank-conflict counts measured on gfx950 within 15%),
+// such a group is conflict-free when its addresses differ mod 16. One more
+// than the padded block (N^3 + N^2 + 1) achieves that for N = 3, 4; for
+// N = 5 it (151) folds the lanes onto 8 bank pairs and 141 spreads them (the
+// unpadded N = 5 block needs 125); for N = 6 the padded plane step (42, even)
+// leaves conflicts that no stride removes, and 253 is as good as any.
 __host__ __device__ constexpr int slot_stride(int n) { return n == 5 ? 141 : n * n * n + n * n + 1; }
 
 // Element stride (doubles) of the accumulator: the three slots, plus a pad
