@@ -168,6 +168,12 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
     const int epb = A.epb;
     const int64_t E = A.geo.E;
     const int64_t SE = E * N3;   // state stride
+    // The workgroup's elements are consecutive (the last workgroup may hold
+    // fewer than epb): its nodes are g0 + idx, idx < nwg, so node-parallel
+    // work indexes global memory by a uniform base and a 32-bit lane offset.
+    const int nel = (int)(E - e0 < epb ? E - e0 : epb);
+    const int nwg = nel * N3;
+    const int64_t g0 = e0 * N3;
     const double gm1 = A.gamma - 1.0;
     const double c1 = A.c1;
     const double pref = reference_pressure(A.Uin, SE, gm1);
@@ -204,14 +210,12 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
 #pragma unroll
     for (int j = 0; j < KS; ++j) {
         const int idx = tid + j * nth;
-        const int eli = idx / N3, node = idx - eli * N3;
-        const int64_t ee = e0 + eli;
-        if (idx < epb * N3 && ee < E) {
-            const double* U = A.Uin + ee * N3 + node;
+        if (idx < nwg) {
+            const double* U = A.Uin + g0 + idx;
 #pragma unroll
             for (int s = 0; s < 5; ++s) su[j][s] = U[s * SE];
             if (MLDS) {
-                const double* Cg = A.geo.Cline + ee * N3 + node;   // same offset in line-major order
+                const double* Cg = A.geo.Cline + g0 + idx;   // same offset in line-major order
 #pragma unroll
                 for (int k = 0; k < NCS; ++k) sc[j][k] = Cg[k * SE];
             }
@@ -260,7 +264,7 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
     for (int j = 0; j < KS; ++j) {
         const int idx = tid + j * nth;
         const int eli = idx / N3, node = idx - eli * N3;
-        if (idx < epb * N3 && e0 + eli < E) {
+        if (idx < nwg) {
             const PrimR q = primitives_ref(su[j][0], su[j][1], su[j][2], su[j][3], su[j][4], gm1, pref);
             double* L = lds + eli * LDSE + pad_node<N>(node);
             L[0] = q.rho;
@@ -341,13 +345,11 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
 #pragma unroll
         for (int j = 0; j < KP; ++j) {
             const int idx = tid + j * nth;
-            const int eli = idx / N3, node = idx - eli * N3;
-            const int64_t ee = e0 + eli;
             pf_iw[j] = 0.0;
 #pragma unroll
             for (int s = 0; s < 5; ++s) pf_a[j][s] = pf_b[j][s] = 0.0;
-            if (idx < epb * N3 && ee < E && mode != MODE_RESIDUAL) {
-                const int64_t g = ee * N3 + node;
+            if (idx < nwg && mode != MODE_RESIDUAL) {
+                const int64_t g = g0 + idx;
                 if (!CWA) pf_iw[j] = A.geo.invWJ[g];
                 const double* pa = mode == MODE_RK1 ? A.Uin : A.acc;
 #pragma unroll
@@ -363,8 +365,8 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
             const int zl = it % N2, eli = it / N2 / 5;
 #pragma unroll
             for (int a = 0; a < N; ++a) zw[j][a] = 0.0;
-            if (CWA && mode != MODE_RESIDUAL && it < epb * 5 * N2 && e0 + eli < E) {
-                const double* iw = A.geo.invWJ + (e0 + eli) * N3 + zl;
+            if (CWA && mode != MODE_RESIDUAL && it < nel * 5 * N2) {
+                const double* iw = A.geo.invWJ + g0 + (eli * N3 + zl);
 #pragma unroll
                 for (int a = 0; a < N; ++a) zw[j][a] = iw[a * N2];
             }
@@ -400,30 +402,23 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
     }
     if (A.source) {
         const double t = (A.tdev ? *A.tdev : A.t) + cstage * dt;
-        for (int idx = tid; idx < epb * N3; idx += nth) {
-            int eli = idx / N3, node = idx - eli * N3;
-            int64_t ee = e0 + eli;
-            if (ee < E) {
-                double qs[5];
-                const double* X = A.geo.X + ee * N3 + node;
-                mms_source(X[0], X[SE], X[2 * SE], t, A.gamma, qs);
-                double wj = 1.0 / A.geo.invWJ[ee * N3 + node];
-                double* x = lr + eli * EBLK + pad_node<N>(node);   // slot 0
+        for (int idx = tid; idx < nwg; idx += nth) {
+            const int eli = idx / N3, node = idx - eli * N3;
+            double qs[5];
+            const double* X = A.geo.X + g0 + idx;
+            mms_source(X[0], X[SE], X[2 * SE], t, A.gamma, qs);
+            const double wj = 1.0 / A.geo.invWJ[g0 + idx];
+            double* x = lr + eli * EBLK + pad_node<N>(node);   // slot 0
 #pragma unroll
-                for (int s = 0; s < 5; ++s) x[s * SPN] -= wj * qs[s];
-            }
+            for (int s = 0; s < 5; ++s) x[s * SPN] -= wj * qs[s];
         }
         __syncthreads();
     }
     if (mode == MODE_RESIDUAL) {
-        for (int idx = tid; idx < epb * N3; idx += nth) {
-            int eli = idx / N3, node = idx - eli * N3;
-            int64_t ee = e0 + eli;
-            if (ee < E) {
+        for (int idx = tid; idx < nwg; idx += nth) {
+            const int eli = idx / N3, node = idx - eli * N3;
 #pragma unroll
-                for (int s = 0; s < 5; ++s)
-                    A.out[s * SE + ee * N3 + node] = rsum(eli, s, node);
-            }
+            for (int s = 0; s < 5; ++s) A.out[s * SE + g0 + idx] = rsum(eli, s, node);
         }
         return;
     }
@@ -439,9 +434,8 @@ __device__ __forceinline__ void stage_body(const StageArgs& A, const int64_t e0,
     for (int j = 0; j < KP; ++j) {
         const int idx = tid + j * nth;
         const int eli = idx / N3, node = idx - eli * N3;
-        const int64_t ee = e0 + eli;
-        if (idx >= epb * N3 || ee >= E) continue;
-        const int64_t g = ee * N3 + node;
+        if (idx >= nwg) continue;
+        const int64_t g = g0 + idx;
 #pragma unroll
         for (int s = 0; s < 5; ++s) {
             const double k = CWA ? -lr[eli * EBLK + s * SPN + pad_node<N>(node)] : -(rsum(eli, s, node) * pf_iw[j]);
